@@ -1,0 +1,235 @@
+/*
+ * hfuse.h -- C ABI of the horizontal-fusion library for AMD gfx950 (MI355X).
+ *
+ * Horizontal fusion (Sec. I-A, Sec. II-B "Horizontal Kernel Fusion", and the
+ * Generate algorithm of Sec. III-A): two independent kernels run as ONE launch.  The threads of a
+ * workgroup are cut into two intervals by thread id, [0, d1) and [d1, d1+d2); each
+ * interval executes one original kernel body, and each body's workgroup barriers
+ * are replaced by barriers that only count the threads of its own interval.  The
+ * fused kernel is functionally equivalent to running the two kernels one after
+ * the other (Sec. I-A, Sec. III-A "Replace Synchronization Barriers").
+ *
+ * On CDNA the interval boundary is a multiple of the 64-lane wavefront, the
+ * dispatch branch is wave-uniform (no divergence), and the per-interval barrier
+ * is an LDS arrival counter (s_barrier always spans the whole workgroup).
+ *
+ * Conventions shared by every entry point
+ *  - All tensor pointers in hf_task are DEVICE pointers on the current HIP device,
+ *    owned by the caller.  The library reads hf_task descriptors only during the
+ *    call and never frees caller memory.
+ *  - `stream` arguments are hipStream_t values passed as void* (NULL = the null
+ *    stream).  Work is enqueued and the call returns without synchronising,
+ *    unless `ms_out` is non-NULL: then the call records HIP events around the
+ *    enqueued work, waits for them and stores the elapsed milliseconds.
+ *  - Every function returns HF_OK (0) or a negative hf_status.  Argument errors
+ *    (HF_EINVAL / HF_EUNSUPPORTED) are detected on the host before any HIP call,
+ *    so they can be exercised without a GPU.  No C++ exception crosses the ABI.
+ *  - Scratch: bn_stats and lds_hist keep per-task partial results and arrival
+ *    counters in device scratch.  If hf_task.scratch is NULL the library uses
+ *    its own arena (one region per concurrently running task of a call,
+ *    allocated on first use, zero-filled, released by hf_shutdown).  A caller
+ *    may pass its own zero-filled region of hf_scratch_bytes() bytes instead;
+ *    every kernel leaves the region zero-filled again when it completes.
+ *    Calls that overlap in time on one device and share a scratch region race.
+ *  - The library is not thread-safe; it uses the current HIP device.
+ */
+#ifndef HFUSE_H
+#define HFUSE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status codes */
+typedef enum {
+  HF_OK = 0,
+  HF_EINVAL = -1,        /* bad argument: null pointer, shape, split, block, cap, mode */
+  HF_EUNSUPPORTED = -2,  /* no compiled instantiation for this (pair, block, cap)       */
+  HF_EHIP = -3,          /* a HIP runtime call failed; see hf_last_hip_error()          */
+  HF_ETIMEOUT = -4,      /* the watchdog (HF_TIMEOUT_MS) expired while waiting          */
+  HF_ENOMEM = -5,        /* device allocation failed                                    */
+  HF_ENOMODEL = -6       /* learned tuner asked for before a model was trained/loaded   */
+} hf_status;
+
+/* ---------------------------------------------------------------- kernel kinds */
+/* The kernel library: the deep-learning kernels of the evaluation (Sec. IV-A,
+ * "Benchmark Kernels") that this library implements, plus an integer mixing loop
+ * standing in for the compute-bound hash kernels. */
+typedef enum {
+  HF_BN_STATS = 0,  /* per-channel mean and biased variance of an NCHW fp32 tensor  */
+  HF_INT_MIX = 1,   /* R rounds of xorshift(13,17,5) + multiply-add per uint32       */
+  HF_IM2COL = 2,    /* image patches -> columns, unfold layout, zero padding         */
+  HF_LDS_HIST = 3,  /* 256-bin histogram of uint8 values (bin = byte value)          */
+  HF_UPSAMPLE = 4,  /* bilinear upsampling by an integer factor, half-pixel centres  */
+  HF_NUM_KINDS = 5
+} hf_kind;
+
+/* One kernel instance.
+ *   kind         hf_kind
+ *   in           device input
+ *                  BN_STATS, IM2COL, UPSAMPLE : float  [n][c][h][w], contiguous
+ *                  INT_MIX                    : uint32 [n]
+ *                  LDS_HIST                   : uint8  [n]
+ *   out0         device output
+ *                  BN_STATS : float mean[c]
+ *                  INT_MIX  : uint32 [n]
+ *                  IM2COL   : float [n][c*kh*kw][Ho*Wo], Ho=(h+2*pad-kh)/stride+1 (same for Wo)
+ *                  LDS_HIST : uint32 counts[256] (overwritten, not accumulated)
+ *                  UPSAMPLE : float [n][c][h*s][w*s]
+ *   out1         BN_STATS: float var[c] (biased, divided by n*h*w); unused otherwise
+ *   scratch      optional caller scratch (see conventions above), or NULL
+ *   n,c,h,w      shape; INT_MIX and LDS_HIST use n as the element count only
+ *   p[4]         INT_MIX : p[0] = rounds R >= 0
+ *                IM2COL  : p[0]=kh, p[1]=kw, p[2]=stride, p[3]=pad
+ *                LDS_HIST: p[0] = number of bins, must be 256
+ *                UPSAMPLE: p[0] = integer scale s in [1, 16]
+ * Input and output buffers must be 4-byte aligned (LDS_HIST input: any) and must
+ * not overlap.  Element counts must stay below 2^31 per buffer. */
+typedef struct {
+  int32_t kind;
+  int32_t p[4];
+  int32_t reserved;
+  const void* in;
+  void* out0;
+  void* out1;
+  void* scratch;
+  int64_t n, c, h, w;
+} hf_task;
+
+/* Two independent kernel instances to be fused (K1 and K2 of the Generate
+ * algorithm, Sec. III-A). */
+typedef struct {
+  hf_task a, b;
+} hf_pair;
+
+/* A fused-launch configuration.
+ *   split_waves  wavefronts of each workgroup given to task a (d1 = 64*split_waves);
+ *                the remaining block/64 - split_waves wavefronts run task b.
+ *   block        workgroup size d0 in lanes: 256, 512 or 1024.
+ *   vgpr_cap     per-lane VGPR bound of the compiled variant (0 = none); one of
+ *                0, 64, 80, 96, 128 (Sec. III-B "Limit Register Usage").
+ *   grid         workgroups per launch; 0 = occupancy-derived default.       */
+typedef struct {
+  int32_t split_waves;
+  int32_t block;
+  int32_t vgpr_cap;
+  int32_t grid;
+} hf_config;
+
+/* ---------------------------------------------------------------- life cycle */
+/* Optional explicit initialisation of the current device (queries properties,
+ * creates events).  Every other entry point initialises lazily. */
+int hf_init(void);
+/* Frees library-owned device memory, events and streams of every device used. */
+int hf_shutdown(void);
+/* Human-readable text for an hf_status; never NULL. */
+const char* hf_strerror(int status);
+/* The last hipError_t value recorded by a failing HIP call (0 if none). */
+int hf_last_hip_error(void);
+/* Library version string. */
+const char* hf_version(void);
+
+/* ---------------------------------------------------------------- validation */
+/* Host-only checks of one task descriptor: kind, non-null pointers, shapes, p[].
+ * Returns HF_OK or HF_EINVAL.  Makes no HIP call. */
+int hf_validate_task(const hf_task* t);
+/* Bytes of scratch that `t` needs (0 for kinds that need none), or a negative
+ * hf_status for an invalid task.  Makes no HIP call. */
+int64_t hf_scratch_bytes(const hf_task* t);
+/* Host-only check of a fused configuration for a pair (split, block, cap, grid)
+ * and of both tasks.  Returns HF_OK, HF_EINVAL or HF_EUNSUPPORTED. */
+int hf_validate_fused(const hf_pair* pr, const hf_config* cfg);
+
+/* ---------------------------------------------------------------- execution */
+/* One kernel alone (the "original" kernel of the pair), workgroup size `block`
+ * (256, 512 or 1024), grid = 0 for the occupancy default.  Its barriers are the
+ * native whole-workgroup barrier. */
+int hf_run_solo(const hf_task* t, int block, int grid, void* stream, float* ms_out);
+
+enum { HF_SERIAL = 0, HF_STREAMS = 1 };
+/* Native baseline (Sec. IV-A "Apply"): the two kernels of the pair launched
+ * separately.  HF_SERIAL: a then b, back to back on stream0.  HF_STREAMS: a on
+ * stream0 and b on stream1, forked from and joined back into stream0 with events
+ * (stream1 may be NULL: the library then uses its own non-blocking stream).  The
+ * timed interval runs from before the first launch to after the last kernel
+ * ends (Sec. IV-A "Execution Time Measurement"). */
+int hf_run_unfused(const hf_pair* pr, int block_a, int block_b, int mode,
+                   void* stream0, void* stream1, float* ms_out);
+
+/* The horizontally fused launch (Generate algorithm, Sec. III-A): one kernel, workgroup size
+ * `block`, the first split_num/split_den of its lanes run task a and the rest
+ * run task b.  split_num*block/split_den must be a positive multiple of 64 that
+ * is smaller than block.  vgpr_cap selects the register-bounded variant
+ * (0 = unbounded). */
+int hf_run_fused(const hf_pair* pr, int split_num, int split_den, int block,
+                 int vgpr_cap, void* stream, float* ms_out);
+/* Same, with an explicit hf_config (also fixes the grid). */
+int hf_run_fused_cfg(const hf_pair* pr, const hf_config* cfg, void* stream,
+                     float* ms_out);
+
+/* ---------------------------------------------------------------- resources */
+typedef struct {
+  int32_t vgprs;          /* VGPRs per lane of the compiled kernel                   */
+  int32_t sgprs;          /* SGPRs per wave                                          */
+  int32_t lds_bytes;      /* static LDS per workgroup                                */
+  int32_t spill_bytes;    /* private (scratch) bytes per lane: register spills       */
+  int32_t wg_per_cu;      /* resident workgroups per CU at this block size           */
+  int32_t waves_per_simd; /* resident wavefronts per SIMD                            */
+  int32_t num_cus;        /* compute units of the device                             */
+  int32_t default_grid;   /* grid hf_run_* uses when grid == 0                       */
+} hf_kernel_info;
+/* Resources of the fused instantiation for (pair kinds, block, cap). */
+int hf_fused_info(int kind_a, int kind_b, int block, int vgpr_cap, hf_kernel_info* out);
+/* Resources of the solo kernel of `kind` at `block`. */
+int hf_solo_info(int kind, int block, hf_kernel_info* out);
+
+/* ---------------------------------------------------------------- tuning */
+enum {
+  HF_TUNE_EXHAUSTIVE = 0, /* every legal (split, block, cap) of the compiled menu     */
+  HF_TUNE_PAPER = 1,      /* Main search of Sec. III-B: d0 = 1024, d1 = 128, 256, ..., 896; each
+                             partition profiled without and with the bound r0       */
+  HF_TUNE_NAIVE = 2,      /* even split, no bound, no search (Sec. IV-A "Naive")     */
+  HF_TUNE_MLP = 3         /* learned cost model ranks all candidates; only the top-k
+                             are profiled                                           */
+};
+typedef struct {
+  int32_t n_candidates;   /* candidates the method considered                        */
+  int32_t n_profiled;     /* candidates actually launched and timed                  */
+  float t_best_ms;        /* median time of the returned configuration               */
+  float t_naive_ms;       /* median time of the even split, block 1024, no cap       */
+  float wall_s;           /* host wall time of the search                            */
+  int32_t reps;           /* timed repetitions per candidate                         */
+} hf_tune_stats;
+/* Searches a fused configuration for the pair (Main search, Sec. III-B).  Each
+ * profiled candidate is launched `HF_TUNE_REPS` (default 20) times after a warm-up
+ * launch; its time is the median.  The choice is the minimum median with the
+ * first-found candidate winning ties (the strict comparison of that search).
+ * `block` restricts EXHAUSTIVE/MLP to one block size (0 = 256, 512 and 1024).
+ * Outputs of the pair's tasks are overwritten by the profiling launches. */
+int hf_tune(const hf_pair* pr, int method, int block, int topk, void* stream,
+            hf_config* best, hf_tune_stats* stats);
+
+/* Register bound r0 of the Main search (Sec. III-B) with gfx950 constants: b_i = R/(d_i*V_i),
+ * b0 = min(b1, b2, LDS_CU/LDS(F), T_CU/d0), r0 = R/(b0*d0), R = 131072 lane
+ * registers per CU, LDS_CU = 163840 bytes, T_CU = 2048 lanes; all divisions
+ * floor.  Inputs are the solo VGPR counts v_a, v_b, the fused kernel's LDS
+ * bytes and the partition sizes.  Returns r0 (>= 1) or HF_EINVAL. */
+int hf_register_bound(int d1, int d2, int vgpr_a, int vgpr_b, int lds_fused);
+
+/* ---------------------------------------------------------------- microbenchmarks */
+/* Streams `bytes` (multiple of 16) from src to dst: the reference copy kernel
+ * for measured HBM ceilings and for scaling rocprof byte counters. */
+int hf_copy(void* dst, const void* src, int64_t bytes, void* stream, float* ms_out);
+/* Writes a library-owned 1 GiB buffer so that no input stays in the 256 MB
+ * last-level cache between timed repetitions. */
+int hf_scrub(void* stream);
+/* Keeps the GPU busy for about `ms` milliseconds (warm-up before measurements,
+ * Sec. IV-A "Execution Time Measurement"). */
+int hf_warmup(int ms, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HFUSE_H */

@@ -1,0 +1,233 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle itself:
+closed forms, a published value, library routines and brute force.
+
+Each test is chosen so that a plausible slip in the oracle (a dropped term, a
+wrong sign, index or divisor, a transposed operand) fails at least one of them.
+"""
+import numpy as np
+import pytest
+import torch
+import torch.nn.functional as F
+
+import oracle
+from paper_2007_01277_amd import inputs
+
+M32 = 0xFFFFFFFF
+K_MUL = 2654435761  # Knuth's multiplicative-hashing constant, 0x9E3779B1
+
+
+# ------------------------------------------------------------------ bn_stats
+def test_bn_constant_input_exact():
+    # every partial sum of 0.75 is exact, so mean = 0.75 and var = 0 exactly
+    x = np.full((3, 5, 7, 9), 0.75, np.float32)
+    m, v = oracle.bn_stats(x)
+    assert np.all(m == 0.75) and np.all(v == 0.0)
+
+
+def test_bn_two_level_closed_form():
+    # half of each channel at a_c - b_c, half at a_c + b_c: mean a_c, biased var b_c^2
+    N, C, H, W = 4, 6, 3, 8
+    a = np.linspace(-3, 5, C).astype(np.float32)
+    b = np.linspace(0.25, 2.0, C).astype(np.float32)
+    sign = np.where((np.arange(N * H * W) % 2) == 0, -1.0, 1.0).reshape(N, 1, H, W)
+    x = (a[None, :, None, None] + sign * b[None, :, None, None]).astype(np.float32)
+    m, v = oracle.bn_stats(x)
+    # closed form from the two float32 levels actually stored: lo and hi
+    lo = (a - b).astype(np.float64)
+    hi = (a + b).astype(np.float64)
+    np.testing.assert_allclose(m, (lo + hi) / 2, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(v, ((hi - lo) / 2) ** 2, rtol=1e-12, atol=0)
+
+
+def test_bn_matches_numpy_population_stats():
+    x = inputs.bn_input((3, 7, 5, 11), seed=5)
+    m, v = oracle.bn_stats(x)
+    xd = x.astype(np.float64).transpose(1, 0, 2, 3).reshape(7, -1)
+    np.testing.assert_allclose(m, xd.mean(axis=1), rtol=1e-12, atol=1e-13)
+    np.testing.assert_allclose(v, xd.var(axis=1, ddof=0), rtol=1e-11, atol=0)
+
+
+def test_bn_empty_channel_rejected():
+    with pytest.raises(ValueError):
+        oracle.bn_stats(np.zeros((0, 3, 4, 4), np.float32))
+
+
+def test_bn_generator_statistics():
+    # the synthetic input follows z*scale_c + shift_c: sample stats of each channel
+    # lie within 5 sigma of their sampling distributions
+    shape = (8, 4, 32, 32)
+    x = inputs.bn_input(shape, seed=11)
+    prm = inputs.rng(12)
+    scale = prm.uniform(0.5, 2.0, size=4).astype(np.float32).astype(np.float64)
+    shift = prm.uniform(-1.0, 1.0, size=4).astype(np.float32).astype(np.float64)
+    m, v = oracle.bn_stats(x)
+    M = 8 * 32 * 32
+    assert np.all(np.abs(m - shift) <= 5 * scale / np.sqrt(M))
+    assert np.all(np.abs(v - scale ** 2) <= 5 * scale ** 2 * np.sqrt(2.0 / M))
+
+
+# ------------------------------------------------------------------ int_mix
+def _unshift_left(y, k):
+    # inverse of x ^= x << k on 32 bits
+    x = y
+    for _ in range(32 // k + 1):
+        x = y ^ ((x << k) & M32)
+    return x
+
+
+def _unshift_right(y, k):
+    x = y
+    for _ in range(32 // k + 1):
+        x = y ^ (x >> k)
+    return x
+
+
+def _int_mix_inverse(y, rounds):
+    kinv = pow(K_MUL, -1, 2 ** 32)
+    x = int(y)
+    for r in reversed(range(rounds)):
+        x = ((x - r) * kinv) & M32
+        x = _unshift_left(x, 5)
+        x = _unshift_right(x, 17)
+        x = _unshift_left(x, 13)
+    return x
+
+
+def test_int_mix_zero_rounds_is_identity():
+    s = inputs.uint32_seeds(1000, seed=3)
+    assert np.array_equal(oracle.int_mix(s, 0), s)
+
+
+def test_int_mix_xorshift_matches_marsaglia_published_value():
+    # Marsaglia, "Xorshift RNGs" (J. Stat. Softw. 8(14), 2003): the 32-bit
+    # generator with shifts (13, 17, 5) from y = 2463534242 first returns 723471715.
+    # One round is that step followed by x*K + 0, so undo the multiply.
+    y = oracle.int_mix(np.array([2463534242], np.uint32), 1)[0]
+    kinv = pow(K_MUL, -1, 2 ** 32)
+    assert (int(y) * kinv) & M32 == 723471715
+
+
+@pytest.mark.parametrize("rounds", [1, 2, 7, 32, 128])
+def test_int_mix_inverts_to_the_seeds(rounds):
+    s = inputs.uint32_seeds(64, seed=rounds)
+    y = oracle.int_mix(s, rounds)
+    back = [_int_mix_inverse(v, rounds) for v in y]
+    assert back == [int(v) for v in s]
+
+
+def test_int_mix_round_index_matters():
+    # 0 is a fixed point of xorshift and of the multiply; only the "+ r" term moves it
+    z = np.zeros(1, np.uint32)
+    assert oracle.int_mix(z, 1)[0] == 0
+    assert oracle.int_mix(z, 2)[0] == 1
+
+
+# ------------------------------------------------------------------ lds_hist
+def test_hist_matches_bincount_and_total():
+    x = inputs.zipf_u8(100_003, seed=4)
+    c = oracle.hist256(x)
+    assert int(c.sum()) == x.size
+    assert np.array_equal(c, np.bincount(x, minlength=256).astype(np.uint64))
+
+
+def test_hist_constant_and_ramp():
+    c = oracle.hist256(np.full(777, 42, np.uint8))
+    assert c[42] == 777 and c.sum() == 777
+    ramp = (np.arange(256 * 13) % 256).astype(np.uint8)
+    assert np.all(oracle.hist256(ramp) == 13)
+
+
+def test_zipf_generator_head_mass():
+    # truncated Zipf(1.2) over 256 ranks: P(rank 1) = 1/H, H = sum k^-1.2
+    H = np.sum(1.0 / np.arange(1, 257) ** 1.2)
+    x = inputs.zipf_u8(400_000, seed=9)
+    p0 = np.mean(x == 0)
+    assert abs(p0 - 1.0 / H) < 5 * np.sqrt((1 / H) * (1 - 1 / H) / x.size)
+
+
+# ------------------------------------------------------------------ im2col
+@pytest.mark.parametrize("shape,k,s,p", [
+    ((2, 3, 7, 9), (3, 3), 1, 1),
+    ((1, 2, 8, 8), (3, 3), 2, 1),
+    ((2, 4, 5, 6), (1, 1), 1, 0),
+    ((1, 3, 6, 5), (2, 3), 1, 0),
+    ((1, 2, 9, 7), (5, 5), 2, 2),
+])
+def test_im2col_matches_torch_unfold(shape, k, s, p):
+    x = inputs.normal_image(shape, seed=1)
+    out = oracle.im2col(x, k[0], k[1], s, p)
+    ref = F.unfold(torch.from_numpy(x), kernel_size=k, stride=s, padding=p).numpy()
+    assert out.shape == ref.shape
+    assert np.array_equal(out, ref)
+
+
+def test_im2col_1x1_is_reshape():
+    x = inputs.normal_image((2, 5, 4, 6), seed=2)
+    out = oracle.im2col(x, 1, 1, 1, 0)
+    assert np.array_equal(out, x.reshape(2, 5, 24))
+
+
+def test_im2col_centre_row_is_input():
+    x = inputs.normal_image((2, 3, 6, 7), seed=3)
+    out = oracle.im2col(x, 3, 3, 1, 1).reshape(2, 3, 9, 42)
+    assert np.array_equal(out[:, :, 4, :], x.reshape(2, 3, 42))
+
+
+def test_im2col_overlap_counts():
+    # folding the columns of an all-ones image back counts how many 3x3 windows
+    # cover each pixel: 9 inside, 6 on an edge, 4 in a corner
+    H, W = 6, 7
+    cols = oracle.im2col(np.ones((1, 1, H, W), np.float32), 3, 3, 1, 1)
+    cnt = F.fold(torch.from_numpy(cols), output_size=(H, W), kernel_size=3, padding=1)[0, 0]
+    expect = np.full((H, W), 9.0)
+    expect[0, :] = expect[-1, :] = expect[:, 0] = expect[:, -1] = 6.0
+    expect[0, 0] = expect[0, -1] = expect[-1, 0] = expect[-1, -1] = 4.0
+    assert np.array_equal(cnt.numpy(), expect)
+
+
+def test_im2col_times_weights_is_direct_convolution():
+    x = inputs.normal_image((2, 3, 6, 5), seed=4)
+    w = inputs.normal_image((4, 3, 3, 3), seed=5)
+    cols = oracle.im2col(x, 3, 3, 1, 1).astype(np.float64)
+    y = np.einsum("ok,nkl->nol", w.reshape(4, 27).astype(np.float64), cols)
+    # brute-force direct convolution, zero padding 1
+    xp = np.zeros((2, 3, 8, 7))
+    xp[:, :, 1:-1, 1:-1] = x
+    ref = np.zeros((2, 4, 6, 5))
+    for n in range(2):
+        for o in range(4):
+            for i in range(6):
+                for j in range(5):
+                    ref[n, o, i, j] = np.sum(xp[n, :, i:i + 3, j:j + 3] * w[o])
+    np.testing.assert_allclose(y.reshape(2, 4, 6, 5), ref, rtol=1e-12, atol=1e-12)
+
+
+# ------------------------------------------------------------------ upsample
+@pytest.mark.parametrize("shape,s", [((2, 3, 5, 7), 2), ((1, 2, 4, 3), 3), ((1, 1, 1, 6), 2),
+                                     ((1, 2, 6, 6), 1), ((1, 1, 3, 4), 4)])
+def test_upsample_matches_torch_interpolate(shape, s):
+    x = inputs.normal_image(shape, seed=6)
+    out = oracle.upsample(x, s)
+    ref = F.interpolate(torch.from_numpy(x).double(), scale_factor=s, mode="bilinear",
+                        align_corners=False).numpy()
+    np.testing.assert_allclose(out, ref, rtol=0, atol=1e-12)
+
+
+def test_upsample_constant_is_exact():
+    out = oracle.upsample(np.full((1, 2, 5, 6), -1.375, np.float32), 2)
+    assert np.all(out == -1.375)
+
+
+def test_upsample_ramp_closed_form():
+    # a ramp along w is reproduced at the clamped source coordinate:
+    # out[ox] = min(max(ox/2 - 1/4, 0), W - 1)
+    W = 9
+    x = np.tile(np.arange(W, dtype=np.float32), (1, 1, 3, 1))
+    out = oracle.upsample(x, 2)[0, 0, 1]
+    ox = np.arange(2 * W)
+    assert np.array_equal(out, np.clip(ox / 2 - 0.25, 0, W - 1))
+
+
+def test_upsample_identity_scale():
+    x = inputs.normal_image((1, 2, 4, 5), seed=7)
+    assert np.array_equal(oracle.upsample(x, 1), x.astype(np.float64))
