@@ -211,6 +211,18 @@ typedef struct {
 int hf_tune(const hf_pair* pr, int method, int block, int topk, void* stream,
             hf_config* best, hf_tune_stats* stats);
 
+/* Median time in milliseconds of `reps` fused launches of `cfg` (after one
+ * untimed launch), each bracketed by HIP events on `stream`. */
+int hf_profile(const hf_pair* pr, const hf_config* cfg, int reps, void* stream, float* median_ms);
+
+/* Host-only: the candidate configurations `method` considers, in the order it
+ * profiles them (before any ranking by the learned model).  vgpr_a, vgpr_b and
+ * lds_fused feed the register bound of HF_TUNE_PAPER (ignored otherwise).
+ * Writes at most `max` entries to `out` (may be NULL) and returns the total
+ * count, or HF_EINVAL. */
+int hf_tune_candidates(int method, int block, int vgpr_a, int vgpr_b, int lds_fused,
+                       hf_config* out, int max);
+
 /* Register bound r0 of the Main search (Sec. III-B) with gfx950 constants: b_i = R/(d_i*V_i),
  * b0 = min(b1, b2, LDS_CU/LDS(F), T_CU/d0), r0 = R/(b0*d0), R = 131072 lane
  * registers per CU, LDS_CU = 163840 bytes, T_CU = 2048 lanes; all divisions

@@ -1,0 +1,466 @@
+// hf_bodies.hpp -- the kernel bodies that horizontal fusion combines.
+//
+// Each body is written once, as a __device__ function of an interval (Part) and
+// a barrier type.  The solo kernel instantiates it with the whole workgroup and
+// the native workgroup barrier; the fused kernel instantiates it with one
+// wavefront-aligned interval and the interval's LDS barrier (Sec. III-A,
+// Generate algorithm: the built-ins threadIdx.x / blockDim.x become the interval
+// variables tid_i / size_i, and __syncthreads becomes the interval barrier).
+//
+// Every body is grid-stride over work units, so it is correct for any grid and
+// any interval size; units whose result is floating point are owned by one
+// wavefront and reduced in a fixed order, so a fused launch reproduces the solo
+// launch bit for bit whatever the split.
+#pragma once
+#include "hf_device.hpp"
+
+namespace hf {
+
+// ======================================================================= args
+// Per-kind kernel arguments, filled on the host from an hf_task.
+
+struct BnArgs {  // per-channel mean / biased variance of NCHW fp32
+  const float* x;
+  float* mean;
+  float* var;
+  uint32_t* ctr;   // [C] chunk arrival counters (zero between launches)
+  uint32_t* part;  // [C][chunks][2] chunk (mean, M2) as float bits
+  uint32_t C, HW, M, CHWm;  // M = N*HW elements per channel, CHWm = (C-1)*HW
+  uint32_t chunks;          // chunks per channel
+  uint32_t total;           // C * chunks
+  uint32_t vec;             // float4 path: HW % 4 == 0 and x 16-byte aligned
+  FastDiv div_hw, div_chunks;
+};
+
+struct MixArgs {  // R rounds of xorshift32 + multiply-add per uint32
+  const uint32_t* in;
+  uint32_t* out;
+  uint32_t n, n4;  // elements, and uint4 vectors in the vector path (0 otherwise)
+  int32_t rounds;
+};
+
+struct HistArgs {  // 256-bin histogram of bytes
+  const uint8_t* in;
+  uint32_t* out;
+  uint32_t* acc;  // [256] merged counts (zero between launches)
+  uint32_t* ctr;  // [1] workgroup arrival counter (zero between launches)
+  uint32_t n;
+  uint32_t head;        // bytes before the first 16-byte aligned address
+  uint32_t n16;         // aligned 16-byte vectors after the head
+  uint32_t tail_start;  // head + 16 * n16
+};
+
+struct Im2colArgs {  // patches -> columns, [N][C*kh*kw][Ho*Wo]
+  const float* x;
+  float* out;
+  uint32_t C, H, W, kw, s, p, Ho, Wo, KK, CKK;
+  uint32_t units;           // N * C * Ho: one unit = (n, c, oh) -> kh*kw output rows
+  uint32_t lanes_per_unit;  // KK * Wo4 (vector) or KK * Wo (scalar)
+  uint32_t vec;             // Wo % 4 == 0 and out 16-byte aligned
+  FastDiv div_ho, div_c, div_row, div_kw;  // div_row: by Wo4 (vector) or Wo
+};
+
+struct UpArgs {  // bilinear upsampling by integer factor s, half-pixel centres
+  const float* x;
+  float* out;
+  uint32_t H, W, Ho, Wo;
+  float inv_s;
+  uint32_t rows;            // N*C*Ho output rows
+  uint32_t rows_per_unit;   // rows handled together when rows are short
+  uint32_t units;           // ceil(rows / rows_per_unit)
+  uint32_t lanes_per_unit;  // rows_per_unit * Wo4 (vector) or * Wo
+  uint32_t vec;             // Wo % 4 == 0 and out 16-byte aligned
+  FastDiv div_ho, div_row;  // div_row: by Wo4 (vector) or Wo
+};
+
+union DevTask {
+  BnArgs bn;
+  MixArgs mix;
+  HistArgs hist;
+  Im2colArgs im2col;
+  UpArgs up;
+};
+
+// Agent-scope helpers for partial results exchanged between workgroups.
+__device__ __forceinline__ void store_agent(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t load_agent(uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Waits until every vector-memory operation this wave issued has completed
+// (s_waitcnt vmcnt(0); expcnt and lgkmcnt left at their maxima, GFX9 encoding).
+// For a store or an atomic, completion means the device-coherent level has
+// acknowledged it.
+__device__ __forceinline__ void wait_vmem() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");  // keeps prior accesses above
+  __builtin_amdgcn_s_waitcnt(0x0F70);
+}
+
+// Arrival on a cross-workgroup counter after publishing results.  Everything a
+// wave publishes for other workgroups goes through device-coherent accesses
+// (agent-scope atomic stores and RMWs, read back with agent-scope atomic loads
+// or RMWs), so no L2 writeback or invalidate is needed: it is enough that those
+// accesses have completed before the arrival is counted.  An agent-scope
+// release would add an L2 writeback, and an acquire an L2 invalidate, to every
+// arrival, which on a multi-XCD part stalls every wave of the die.  The wave
+// that sees itself as the last arrival reads the published data only with
+// agent-scope atomic loads or RMWs issued after its counter RMW returned.
+__device__ __forceinline__ uint32_t arrive_after_coherent_stores(uint32_t* ctr) {
+  wait_vmem();
+  return __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ================================================================== bn_stats
+// Statistics kernel of the normalisation example (Sec. II-C): per-channel mean
+// and variance of x[N][C][H][W].
+//
+// Work decomposition (independent of grid and interval size):
+//   unit  = 1024 consecutive elements of one channel's N*H*W sequence; one
+//           wavefront loads it (16 values per lane), and computes the unit's
+//           mean and M2 by two passes over registers with fixed-order wave sums;
+//   chunk = 4 consecutive units; the wavefront merges its units in order with
+//           Chan's pairwise update and publishes (mean, M2) of the chunk;
+//   the wavefront that publishes a channel's last chunk (arrival counter) merges
+//           the channel's chunks in double and writes mean[c], var[c].
+struct BnStats {
+  static constexpr uint32_t kUnit = 1024;
+  static constexpr uint32_t kChunkUnits = 4;
+  static constexpr uint32_t kChunk = kUnit * kChunkUnits;
+  static constexpr uint32_t lds_words(int) { return 0; }
+
+  // one unit: 16 values per lane, lane-major so every load is coalesced
+  struct Regs {
+    float v[16];
+  };
+
+  __device__ static __forceinline__ void load_unit(const BnArgs& a, uint32_t c, uint32_t ubase,
+                                                   uint32_t lane, Regs& r) {
+    if (a.vec) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const uint32_t j = ubase + 4u * (lane + 64u * t);
+        float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (j < a.M) {
+          const uint32_t n = fdiv(j, a.div_hw);
+          q = *reinterpret_cast<const float4*>(a.x + (c * a.HW + j + n * a.CHWm));
+        }
+        r.v[4 * t + 0] = q.x;
+        r.v[4 * t + 1] = q.y;
+        r.v[4 * t + 2] = q.z;
+        r.v[4 * t + 3] = q.w;
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < 16; ++t) {
+        const uint32_t j = ubase + lane + 64u * t;
+        float q = 0.f;
+        if (j < a.M) {
+          const uint32_t n = fdiv(j, a.div_hw);
+          q = a.x[c * a.HW + j + n * a.CHWm];
+        }
+        r.v[t] = q;
+      }
+    }
+  }
+
+  __device__ static __forceinline__ bool valid(const BnArgs& a, uint32_t ubase, uint32_t lane,
+                                               int t) {
+    const uint32_t j = a.vec ? ubase + 4u * (lane + 64u * (t >> 2)) + (t & 3)
+                             : ubase + lane + 64u * t;
+    return j < a.M;
+  }
+
+  template <class Bar>
+  __device__ static void run(const DevTask& dt, const Part& p, Bar&, uint32_t*) {
+    const BnArgs& a = dt.bn;
+    const uint32_t lane = lane_id();
+    const uint32_t nw = p.nwg * p.nwaves;
+    for (uint32_t chunk = p.wg * p.nwaves + p.wave; chunk < a.total; chunk += nw) {
+      const uint32_t c = fdiv(chunk, a.div_chunks);
+      const uint32_t k = chunk - c * a.chunks;
+      const uint32_t ebeg = k * kChunk;
+      const uint32_t eend = min(a.M, ebeg + kChunk);
+      float cnt = 0.f, mean = 0.f, m2 = 0.f;
+      Regs cur, nxt;
+      load_unit(a, c, ebeg, lane, cur);
+      for (uint32_t ub = ebeg; ub < eend; ub += kUnit) {
+        const bool more = ub + kUnit < eend;
+        if (more) load_unit(a, c, ub + kUnit, lane, nxt);  // next unit in flight
+        const float nu = (float)min(kUnit, eend - ub);
+        float s = 0.f;
+#pragma unroll
+        for (int t = 0; t < 16; ++t) s += cur.v[t];
+        const float mu = wave_sum(s) / nu;
+        float q = 0.f;
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+          const float d = valid(a, ub, lane, t) ? cur.v[t] - mu : 0.f;
+          q += d * d;
+        }
+        const float m2u = wave_sum(q);
+        // Chan et al. pairwise update of (cnt, mean, m2) with (nu, mu, m2u)
+        const float nab = cnt + nu;
+        const float delta = mu - mean;
+        mean = mean + delta * (nu / nab);
+        m2 = m2 + m2u + delta * delta * (cnt * nu / nab);
+        cnt = nab;
+        if (more) cur = nxt;
+      }
+      // publish the chunk, then count it
+      uint32_t old = 0;
+      if (lane == 0) {
+        store_agent(a.part + 2u * chunk + 0u, __builtin_bit_cast(uint32_t, mean));
+        store_agent(a.part + 2u * chunk + 1u, __builtin_bit_cast(uint32_t, m2));
+        old = arrive_after_coherent_stores(a.ctr + c);
+      }
+      old = uniform(old);
+      if (old == a.chunks - 1u) finish_channel(a, c, lane);
+    }
+  }
+
+  // Merge the chunks of channel c in double: mean = sum n_k mean_k / M,
+  // M2 = sum (M2_k + n_k (mean_k - mean)^2), var = M2 / M.
+  __device__ static void finish_channel(const BnArgs& a, uint32_t c, uint32_t lane) {
+    const uint32_t base = 2u * c * a.chunks;
+    double s = 0.0;
+    for (uint32_t k = lane; k < a.chunks; k += 64u) {
+      const double nk = (double)min(kChunk, a.M - k * kChunk);
+      s += nk * (double)__builtin_bit_cast(float, load_agent(a.part + base + 2u * k));
+    }
+    const double mu = wave_sum_f64(s) / (double)a.M;
+    double q = 0.0;
+    for (uint32_t k = lane; k < a.chunks; k += 64u) {
+      const double nk = (double)min(kChunk, a.M - k * kChunk);
+      const double mk = (double)__builtin_bit_cast(float, load_agent(a.part + base + 2u * k));
+      const double m2k = (double)__builtin_bit_cast(float, load_agent(a.part + base + 2u * k + 1u));
+      const double d = mk - mu;
+      q += m2k + nk * d * d;
+    }
+    const double var = wave_sum_f64(q) / (double)a.M;
+    // leave the scratch zero-filled, as every kernel of the library does
+    for (uint32_t k = lane; k < a.chunks; k += 64u) {
+      store_agent(a.part + base + 2u * k, 0u);
+      store_agent(a.part + base + 2u * k + 1u, 0u);
+    }
+    if (lane == 0) {
+      a.mean[c] = (float)mu;
+      a.var[c] = (float)var;
+      store_agent(a.ctr + c, 0u);  // leave the counter zero for the next launch
+    }
+  }
+};
+
+// ================================================================== int_mix
+// Integer mixing loop standing in for the compute-bound hash kernels: per element
+// R rounds of  x ^= x<<13; x ^= x>>17; x ^= x<<5; x = x*2654435761 + r  (mod 2^32).
+struct IntMix {
+  static constexpr uint32_t lds_words(int) { return 0; }
+
+  __device__ static __forceinline__ uint32_t round1(uint32_t x, uint32_t r) {
+    x ^= x << 13;
+    x ^= x >> 17;
+    x ^= x << 5;
+    return x * 2654435761u + r;
+  }
+
+  template <class Bar>
+  __device__ static void run(const DevTask& dt, const Part& p, Bar&, uint32_t*) {
+    const MixArgs& a = dt.mix;
+    const uint32_t gl = p.wg * p.nlanes + p.lane;
+    const uint32_t stride = p.nwg * p.nlanes;
+    const uint32_t R = (uint32_t)a.rounds;
+    const uint4* in4 = reinterpret_cast<const uint4*>(a.in);
+    uint4* out4 = reinterpret_cast<uint4*>(a.out);
+    for (uint32_t i = gl; i < a.n4; i += stride) {
+      uint4 v = in4[i];
+      for (uint32_t r = 0; r < R; ++r) {  // four independent chains per lane
+        v.x = round1(v.x, r);
+        v.y = round1(v.y, r);
+        v.z = round1(v.z, r);
+        v.w = round1(v.w, r);
+      }
+      out4[i] = v;
+    }
+    for (uint32_t i = 4u * a.n4 + gl; i < a.n; i += stride) {
+      uint32_t x = a.in[i];
+      for (uint32_t r = 0; r < R; ++r) x = round1(x, r);
+      a.out[i] = x;
+    }
+  }
+};
+
+// ================================================================== lds_hist
+// Histogram kernel of Sec. II-C: clear shared-memory bins, count with shared-
+// memory atomics, merge the bins into the global counts.  Each wavefront owns
+// one copy of the 256 bins in LDS, so atomics of different wavefronts never
+// collide; the interval's barriers separate clearing, counting and merging.
+// The workgroups add their bins into an agent-scope accumulator; the last
+// workgroup to arrive moves the totals to the output and re-zeroes it.
+struct LdsHist {
+  static constexpr uint32_t lds_words(int block) { return (uint32_t)(block / 64) * 256u; }
+
+  __device__ static __forceinline__ void count_byte(uint32_t* bins, uint32_t b) {
+    __hip_atomic_fetch_add(bins + b, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+  __device__ static __forceinline__ void count_word(uint32_t* bins, uint32_t w) {
+    count_byte(bins, w & 0xFFu);
+    count_byte(bins, (w >> 8) & 0xFFu);
+    count_byte(bins, (w >> 16) & 0xFFu);
+    count_byte(bins, w >> 24);
+  }
+
+  template <class Bar>
+  __device__ static void run(const DevTask& dt, const Part& p, Bar& bar, uint32_t* lds) {
+    const HistArgs& a = dt.hist;
+    const uint32_t lane = lane_id();
+    for (uint32_t i = p.lane; i < p.nwaves * 256u; i += p.nlanes) lds[i] = 0u;
+    bar.sync();
+
+    uint32_t* mine = lds + p.wave * 256u;
+    const uint32_t gl = p.wg * p.nlanes + p.lane;
+    const uint32_t stride = p.nwg * p.nlanes;
+    const uint4* v16 = reinterpret_cast<const uint4*>(a.in + a.head);
+    for (uint32_t i = gl; i < a.n16; i += stride) {
+      const uint4 q = v16[i];
+      count_word(mine, q.x);
+      count_word(mine, q.y);
+      count_word(mine, q.z);
+      count_word(mine, q.w);
+    }
+    if (gl < a.head) count_byte(mine, a.in[gl]);
+    for (uint32_t i = a.tail_start + gl; i < a.n; i += stride) count_byte(mine, a.in[i]);
+    bar.sync();
+
+    for (uint32_t b = p.lane; b < 256u; b += p.nlanes) {
+      uint32_t s = 0;
+      for (uint32_t w = 0; w < p.nwaves; ++w) s += lds[w * 256u + b];
+      if (s) __hip_atomic_fetch_add(a.acc + b, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    wait_vmem();  // this wave's merge atomics have completed ...
+    bar.sync();   // ... before wave 0 of the interval counts the workgroup in
+
+    if (p.wave == 0) {
+      uint32_t old = 0;
+      if (lane == 0) old = arrive_after_coherent_stores(a.ctr);
+      old = uniform(old);
+      if (old == p.nwg - 1u) {
+        for (uint32_t b = lane; b < 256u; b += 64u)
+          a.out[b] = __hip_atomic_exchange(a.acc + b, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (lane == 0) store_agent(a.ctr, 0u);
+      }
+    }
+  }
+};
+
+// ================================================================== im2col
+// Im2Col (Sec. IV-A): out[n][(c*kh + i)*kw + j][oh*Wo + ow] = x[n][c][oh*s-p+i][ow*s-p+j],
+// zero outside the image.  A unit is one (n, c, oh): its kh*kw output row
+// segments of length Wo, written as float4 when Wo % 4 == 0.
+struct Im2col {
+  static constexpr uint32_t lds_words(int) { return 0; }
+
+  template <class Bar>
+  __device__ static void run(const DevTask& dt, const Part& p, Bar&, uint32_t*) {
+    const Im2colArgs& a = dt.im2col;
+    const uint32_t lane = lane_id();
+    const uint32_t nw = p.nwg * p.nwaves;
+    const uint32_t HW = a.H * a.W;
+    for (uint32_t u = p.wg * p.nwaves + p.wave; u < a.units; u += nw) {
+      const uint32_t nc = fdiv(u, a.div_ho);
+      const uint32_t oh = u - nc * a.Ho;
+      const uint32_t n = fdiv(nc, a.div_c);
+      const uint32_t c = nc - n * a.C;
+      const float* img = a.x + nc * HW;
+      float* obase = a.out + ((n * a.CKK + c * a.KK) * a.Ho + oh) * a.Wo;
+      const uint32_t rowstride = a.Ho * a.Wo;  // between consecutive kernel offsets
+      for (uint32_t t = lane; t < a.lanes_per_unit; t += 64u) {
+        const uint32_t kk = fdiv(t, a.div_row);
+        const uint32_t col = t - kk * a.div_row.d;  // ow4 (vector) or ow (scalar)
+        const uint32_t i = fdiv(kk, a.div_kw);
+        const uint32_t j = kk - i * a.kw;
+        const int ih = (int)(oh * a.s + i) - (int)a.p;
+        const bool rowok = ih >= 0 && ih < (int)a.H;
+        const float* src = img + (rowok ? ih : 0) * (int)a.W;
+        float* dst = obase + kk * rowstride;
+        if (a.vec) {
+          float v[4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int iw = (int)((4u * col + e) * a.s + j) - (int)a.p;
+            v[e] = (rowok && iw >= 0 && iw < (int)a.W) ? src[iw] : 0.f;
+          }
+          *reinterpret_cast<float4*>(dst + 4u * col) = make_float4(v[0], v[1], v[2], v[3]);
+        } else {
+          const int iw = (int)(col * a.s + j) - (int)a.p;
+          dst[col] = (rowok && iw >= 0 && iw < (int)a.W) ? src[iw] : 0.f;
+        }
+      }
+    }
+  }
+};
+
+// ================================================================== upsample
+// Bilinear upsampling (Sec. IV-A) by an integer factor s with half-pixel
+// centres: t = max(0, (o + 0.5)/s - 0.5), i0 = floor(t), i1 = min(i0+1, L-1),
+// l = t - i0; lerp along x on rows y0 and y1, then along y, as a + l*(b - a).
+struct Upsample {
+  static constexpr uint32_t lds_words(int) { return 0; }
+
+  __device__ static __forceinline__ void coord(uint32_t o, float inv_s, uint32_t L, uint32_t& i0,
+                                               uint32_t& i1, float& l) {
+    const float t = fmaxf(((float)o + 0.5f) * inv_s - 0.5f, 0.f);
+    uint32_t a = (uint32_t)t;
+    a = min(a, L - 1u);
+    i0 = a;
+    i1 = min(a + 1u, L - 1u);
+    l = t - (float)a;
+  }
+
+  __device__ static __forceinline__ float sample(const float* img, uint32_t W, uint32_t y0,
+                                                 uint32_t y1, float ly, uint32_t ox, float inv_s) {
+    uint32_t x0, x1;
+    float lx;
+    coord(ox, inv_s, W, x0, x1, lx);
+    const float a = img[y0 * W + x0], b = img[y0 * W + x1];
+    const float c = img[y1 * W + x0], d = img[y1 * W + x1];
+    const float top = a + lx * (b - a);
+    const float bot = c + lx * (d - c);
+    return top + ly * (bot - top);
+  }
+
+  template <class Bar>
+  __device__ static void run(const DevTask& dt, const Part& p, Bar&, uint32_t*) {
+    const UpArgs& a = dt.up;
+    const uint32_t lane = lane_id();
+    const uint32_t nw = p.nwg * p.nwaves;
+    const uint32_t HW = a.H * a.W;
+    for (uint32_t u = p.wg * p.nwaves + p.wave; u < a.units; u += nw) {
+      const uint32_t row0 = u * a.rows_per_unit;
+      for (uint32_t t = lane; t < a.lanes_per_unit; t += 64u) {
+        const uint32_t rr = fdiv(t, a.div_row);
+        const uint32_t col = t - rr * a.div_row.d;
+        const uint32_t row = row0 + rr;
+        if (row >= a.rows) continue;
+        const uint32_t plane = fdiv(row, a.div_ho);
+        const uint32_t oy = row - plane * a.Ho;
+        uint32_t y0, y1;
+        float ly;
+        coord(oy, a.inv_s, a.H, y0, y1, ly);
+        const float* img = a.x + plane * HW;
+        float* dst = a.out + row * a.Wo;
+        if (a.vec) {
+          float v[4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) v[e] = sample(img, a.W, y0, y1, ly, 4u * col + e, a.inv_s);
+          *reinterpret_cast<float4*>(dst + 4u * col) = make_float4(v[0], v[1], v[2], v[3]);
+        } else {
+          dst[col] = sample(img, a.W, y0, y1, ly, col, a.inv_s);
+        }
+      }
+    }
+  }
+};
+
+}  // namespace hf

@@ -1,0 +1,132 @@
+// hf_device.hpp -- device-side building blocks of the fused kernels (gfx950).
+//
+//  * Part         : the prologue variables of a fused kernel (Sec. III-A, Generate
+//                   algorithm): the thread id and size of the interval a lane
+//                   belongs to, here at wavefront granularity.
+//  * WGBarrier    : the original kernels' workgroup barrier (s_barrier).
+//  * PartBarrier  : the partition-scoped barrier that replaces it inside a fused
+//                   kernel (Sec. III-A "Replace Synchronization Barriers").  CDNA
+//                   has no counted named barriers, so arrivals are counted in LDS:
+//                   one arrival per wavefront, waiters sleep between polls.
+//  * wave_sum     : a fixed-order wavefront reduction built from DPP row moves
+//                   and lane reads, so the same inputs give the same bits in a
+//                   solo and in a fused kernel, whatever the partition size.
+//  * FastDiv      : division by a run-time constant as multiply-high + shift.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hf {
+
+constexpr int kWave = 64;
+
+// Interval of the fused workgroup that the calling lane belongs to.
+struct Part {
+  uint32_t lane;    // lane index inside the interval, 0 .. nlanes-1
+  uint32_t nlanes;  // lanes in the interval (multiple of 64)
+  uint32_t wave;    // wavefront index inside the interval (wave-uniform)
+  uint32_t nwaves;  // wavefronts in the interval
+  uint32_t wg;      // workgroup index
+  uint32_t nwg;     // workgroups in the launch
+};
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint32_t uniform(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+
+// ----------------------------------------------------------------- barriers
+struct WGBarrier {
+  __device__ __forceinline__ void sync() { __syncthreads(); }
+};
+
+// Arrival counter in LDS, monotonically increasing during one launch.  The k-th
+// barrier of an interval of W wavefronts completes when the counter reaches k*W.
+// Every wavefront of the interval must call sync() the same number of times, in
+// wave-uniform control flow.  The counter must be zeroed, and the zero made
+// visible with a whole-workgroup barrier, before the intervals branch apart.
+struct PartBarrier {
+  uint32_t* ctr;
+  uint32_t nwaves;
+  uint32_t target;
+  __device__ __forceinline__ PartBarrier(uint32_t* c, uint32_t w) : ctr(c), nwaves(w), target(0) {}
+  __device__ __forceinline__ void sync() {
+    target += nwaves;
+    // make this wave's LDS and global writes visible inside the workgroup
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    if (lane_id() == 0) {
+      __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      while ((int32_t)(__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) -
+                       target) < 0)
+        __builtin_amdgcn_s_sleep(1);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  }
+};
+
+// ----------------------------------------------------------------- reductions
+// DPP controls (GFX9 encoding): quad_perm [1,0,3,2] = 0xB1, [2,3,0,1] = 0x4E,
+// row_half_mirror = 0x141, row_mirror = 0x140.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float v) {
+  return __builtin_bit_cast(float,
+                            __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, true));
+}
+
+__device__ __forceinline__ float readlane_f32(float v, int l) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+
+// Sum over the 64 lanes; every lane must be active.  After the four DPP steps
+// each 16-lane row holds its row sum in every lane; the four row sums are then
+// added in a fixed order.  Commutativity makes every lane's value identical.
+__device__ __forceinline__ float wave_sum(float v) {
+  v += dpp_f32<0xB1>(v);
+  v += dpp_f32<0x4E>(v);
+  v += dpp_f32<0x141>(v);
+  v += dpp_f32<0x140>(v);
+  const float r0 = readlane_f32(v, 0), r1 = readlane_f32(v, 16);
+  const float r2 = readlane_f32(v, 32), r3 = readlane_f32(v, 48);
+  return (r0 + r1) + (r2 + r3);
+}
+
+// Butterfly sum in double through ds_bpermute; identical result in every lane.
+__device__ __forceinline__ double wave_sum_f64(double v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, kWave);
+  return v;
+}
+
+// ----------------------------------------------------------------- division
+// q = n / d for 0 <= n < 2^31: with l = ceil(log2 d) and m = ceil(2^(31+l) / d),
+// floor(n*m / 2^(31+l)) = floor(n/d) (Granlund & Montgomery, PLDI 1994), and m
+// fits in 32 bits.  For d >= 2 the shift is >= 32, so only the high word of the
+// product is needed.  d == 1 is flagged by m == 0.
+struct FastDiv {
+  uint32_t d;
+  uint32_t m;
+  uint32_t sh;  // 31 + l - 32
+};
+
+inline FastDiv make_fastdiv(uint32_t d) {
+  FastDiv f;
+  f.d = d;
+  if (d <= 1) {
+    f.m = 0;
+    f.sh = 0;
+    return f;
+  }
+  uint32_t l = 0;
+  while ((1ull << l) < d) ++l;
+  const uint64_t num = 1ull << (31 + l);  // l <= 31, so this fits
+  f.m = (uint32_t)((num + d - 1) / d);
+  f.sh = 31 + l - 32;
+  return f;
+}
+
+__host__ __device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv& f) {
+  return f.m == 0 ? n : ((uint32_t)(((uint64_t)n * f.m) >> 32) >> f.sh);
+}
+
+}  // namespace hf

@@ -1,0 +1,298 @@
+"""ctypes binding of libhfuse.so (the C ABI in include/hfuse.h).
+
+Argument marshalling only: torch tensors become device pointers and shapes,
+torch streams become hipStream_t handles.  Every step of the hot path runs in
+the library's HIP kernels; there is no fallback.  If the library is not built,
+``lib()`` raises instead of computing anything another way.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libhfuse.so")
+
+HF_OK, HF_EINVAL, HF_EUNSUPPORTED, HF_EHIP, HF_ETIMEOUT, HF_ENOMEM, HF_ENOMODEL = 0, -1, -2, -3, -4, -5, -6
+HF_BN_STATS, HF_INT_MIX, HF_IM2COL, HF_LDS_HIST, HF_UPSAMPLE = range(5)
+KIND_NAMES = ["bn_stats", "int_mix", "im2col", "lds_hist", "upsample"]
+HF_SERIAL, HF_STREAMS = 0, 1
+HF_TUNE_EXHAUSTIVE, HF_TUNE_PAPER, HF_TUNE_NAIVE, HF_TUNE_MLP = range(4)
+CAPS = (0, 64, 80, 96, 128)
+
+
+class HFError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {status} ({_strerror(status)})")
+
+
+class hf_task(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("p", ctypes.c_int32 * 4), ("reserved", ctypes.c_int32),
+                ("in_", ctypes.c_void_p), ("out0", ctypes.c_void_p), ("out1", ctypes.c_void_p),
+                ("scratch", ctypes.c_void_p),
+                ("n", ctypes.c_int64), ("c", ctypes.c_int64), ("h", ctypes.c_int64), ("w", ctypes.c_int64)]
+
+
+class hf_pair(ctypes.Structure):
+    _fields_ = [("a", hf_task), ("b", hf_task)]
+
+
+class hf_config(ctypes.Structure):
+    _fields_ = [("split_waves", ctypes.c_int32), ("block", ctypes.c_int32),
+                ("vgpr_cap", ctypes.c_int32), ("grid", ctypes.c_int32)]
+
+    def as_tuple(self):
+        return (self.split_waves, self.block, self.vgpr_cap, self.grid)
+
+    def __repr__(self):
+        return f"hf_config(split_waves={self.split_waves}, block={self.block}, vgpr_cap={self.vgpr_cap}, grid={self.grid})"
+
+
+class hf_kernel_info(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in (
+        "vgprs", "sgprs", "lds_bytes", "spill_bytes", "wg_per_cu", "waves_per_simd", "num_cus", "default_grid")]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+class hf_tune_stats(ctypes.Structure):
+    _fields_ = [("n_candidates", ctypes.c_int32), ("n_profiled", ctypes.c_int32),
+                ("t_best_ms", ctypes.c_float), ("t_naive_ms", ctypes.c_float),
+                ("wall_s", ctypes.c_float), ("reps", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_F = ctypes.POINTER(ctypes.c_float)
+
+# name -> (restype, argtypes); the exported surface of include/hfuse.h
+SIGNATURES = {
+    "hf_init": (_I, []),
+    "hf_shutdown": (_I, []),
+    "hf_strerror": (ctypes.c_char_p, [_I]),
+    "hf_last_hip_error": (_I, []),
+    "hf_version": (ctypes.c_char_p, []),
+    "hf_validate_task": (_I, [ctypes.POINTER(hf_task)]),
+    "hf_scratch_bytes": (ctypes.c_int64, [ctypes.POINTER(hf_task)]),
+    "hf_validate_fused": (_I, [ctypes.POINTER(hf_pair), ctypes.POINTER(hf_config)]),
+    "hf_run_solo": (_I, [ctypes.POINTER(hf_task), _I, _I, _P, _F]),
+    "hf_run_unfused": (_I, [ctypes.POINTER(hf_pair), _I, _I, _I, _P, _P, _F]),
+    "hf_run_fused": (_I, [ctypes.POINTER(hf_pair), _I, _I, _I, _I, _P, _F]),
+    "hf_run_fused_cfg": (_I, [ctypes.POINTER(hf_pair), ctypes.POINTER(hf_config), _P, _F]),
+    "hf_fused_info": (_I, [_I, _I, _I, _I, ctypes.POINTER(hf_kernel_info)]),
+    "hf_solo_info": (_I, [_I, _I, ctypes.POINTER(hf_kernel_info)]),
+    "hf_profile": (_I, [ctypes.POINTER(hf_pair), ctypes.POINTER(hf_config), _I, _P, _F]),
+    "hf_tune_candidates": (_I, [_I, _I, _I, _I, _I, ctypes.POINTER(hf_config), _I]),
+    "hf_tune": (_I, [ctypes.POINTER(hf_pair), _I, _I, _I, _P, ctypes.POINTER(hf_config),
+                     ctypes.POINTER(hf_tune_stats)]),
+    "hf_register_bound": (_I, [_I, _I, _I, _I, _I]),
+    "hf_copy": (_I, [_P, _P, ctypes.c_int64, _P, _F]),
+    "hf_scrub": (_I, [_P]),
+    "hf_warmup": (_I, [_I, _P]),
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _strerror(status: int) -> str:
+    try:
+        return lib().hf_strerror(status).decode()
+    except Exception:  # library not loadable: still report the number
+        return "?"
+
+
+def _check(status: int, what: str) -> int:
+    if status < 0:
+        raise HFError(status, what)
+    return status
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+# ------------------------------------------------------------------ descriptors
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def task_bn_stats(x, mean, var) -> hf_task:
+    t = hf_task()
+    t.kind = HF_BN_STATS
+    t.in_, t.out0, t.out1 = _ptr(x), _ptr(mean), _ptr(var)
+    t.n, t.c, t.h, t.w = x.shape
+    return t
+
+
+def task_int_mix(seeds, out, rounds: int) -> hf_task:
+    t = hf_task()
+    t.kind = HF_INT_MIX
+    t.p[0] = rounds
+    t.in_, t.out0 = _ptr(seeds), _ptr(out)
+    t.n = seeds.numel()
+    return t
+
+
+def task_im2col(x, out, kh: int, kw: int, stride: int, pad: int) -> hf_task:
+    t = hf_task()
+    t.kind = HF_IM2COL
+    t.p[0], t.p[1], t.p[2], t.p[3] = kh, kw, stride, pad
+    t.in_, t.out0 = _ptr(x), _ptr(out)
+    t.n, t.c, t.h, t.w = x.shape
+    return t
+
+
+def task_lds_hist(x, counts) -> hf_task:
+    t = hf_task()
+    t.kind = HF_LDS_HIST
+    t.p[0] = 256
+    t.in_, t.out0 = _ptr(x), _ptr(counts)
+    t.n = x.numel()
+    return t
+
+
+def task_upsample(x, out, scale: int) -> hf_task:
+    t = hf_task()
+    t.kind = HF_UPSAMPLE
+    t.p[0] = scale
+    t.in_, t.out0 = _ptr(x), _ptr(out)
+    t.n, t.c, t.h, t.w = x.shape
+    return t
+
+
+def make_pair(a: hf_task, b: hf_task) -> hf_pair:
+    return hf_pair(a, b)
+
+
+# ------------------------------------------------------------------ entry points
+def hf_init():
+    return _check(lib().hf_init(), "hf_init")
+
+
+def hf_shutdown():
+    return _check(lib().hf_shutdown(), "hf_shutdown")
+
+
+def hf_validate_task(t: hf_task) -> int:
+    return lib().hf_validate_task(ctypes.byref(t))
+
+
+def hf_scratch_bytes(t: hf_task) -> int:
+    return lib().hf_scratch_bytes(ctypes.byref(t))
+
+
+def hf_validate_fused(pr: hf_pair, cfg: hf_config) -> int:
+    return lib().hf_validate_fused(ctypes.byref(pr), ctypes.byref(cfg))
+
+
+def _ms(timed):
+    return ctypes.c_float(0.0) if timed else None
+
+
+def hf_run_solo(t: hf_task, block: int = 256, grid: int = 0, stream=None, timed=False):
+    ms = _ms(timed)
+    _check(lib().hf_run_solo(ctypes.byref(t), block, grid, _stream(stream),
+                             ctypes.byref(ms) if ms is not None else None), "hf_run_solo")
+    return ms.value if ms is not None else None
+
+
+def hf_run_unfused(pr: hf_pair, block_a: int = 256, block_b: int = 256, mode: int = HF_SERIAL,
+                   stream0=None, stream1=None, timed=False):
+    ms = _ms(timed)
+    s1 = None if stream1 is None else _stream(stream1)
+    _check(lib().hf_run_unfused(ctypes.byref(pr), block_a, block_b, mode, _stream(stream0), s1,
+                                ctypes.byref(ms) if ms is not None else None), "hf_run_unfused")
+    return ms.value if ms is not None else None
+
+
+def hf_run_fused(pr: hf_pair, split_num: int = 1, split_den: int = 2, block: int = 256,
+                 vgpr_cap: int = 0, stream=None, timed=False):
+    ms = _ms(timed)
+    _check(lib().hf_run_fused(ctypes.byref(pr), split_num, split_den, block, vgpr_cap, _stream(stream),
+                              ctypes.byref(ms) if ms is not None else None), "hf_run_fused")
+    return ms.value if ms is not None else None
+
+
+def hf_run_fused_cfg(pr: hf_pair, cfg: hf_config, stream=None, timed=False):
+    ms = _ms(timed)
+    _check(lib().hf_run_fused_cfg(ctypes.byref(pr), ctypes.byref(cfg), _stream(stream),
+                                  ctypes.byref(ms) if ms is not None else None), "hf_run_fused_cfg")
+    return ms.value if ms is not None else None
+
+
+def hf_fused_info(kind_a: int, kind_b: int, block: int, vgpr_cap: int = 0) -> dict:
+    info = hf_kernel_info()
+    _check(lib().hf_fused_info(kind_a, kind_b, block, vgpr_cap, ctypes.byref(info)), "hf_fused_info")
+    return info.as_dict()
+
+
+def hf_solo_info(kind: int, block: int) -> dict:
+    info = hf_kernel_info()
+    _check(lib().hf_solo_info(kind, block, ctypes.byref(info)), "hf_solo_info")
+    return info.as_dict()
+
+
+def hf_profile(pr: hf_pair, cfg: hf_config, reps: int = 20, stream=None) -> float:
+    ms = ctypes.c_float(0.0)
+    _check(lib().hf_profile(ctypes.byref(pr), ctypes.byref(cfg), reps, _stream(stream), ctypes.byref(ms)),
+           "hf_profile")
+    return ms.value
+
+
+def hf_tune_candidates(method: int, block: int = 0, vgpr_a: int = 32, vgpr_b: int = 32, lds_fused: int = 0):
+    n = _check(lib().hf_tune_candidates(method, block, vgpr_a, vgpr_b, lds_fused, None, 0), "hf_tune_candidates")
+    arr = (hf_config * max(n, 1))()
+    lib().hf_tune_candidates(method, block, vgpr_a, vgpr_b, lds_fused, arr, n)
+    return [arr[i] for i in range(n)]
+
+
+def hf_tune(pr: hf_pair, method: int = HF_TUNE_EXHAUSTIVE, block: int = 0, topk: int = 3, stream=None):
+    best = hf_config()
+    stats = hf_tune_stats()
+    _check(lib().hf_tune(ctypes.byref(pr), method, block, topk, _stream(stream), ctypes.byref(best),
+                         ctypes.byref(stats)), "hf_tune")
+    return best, stats.as_dict()
+
+
+def hf_register_bound(d1: int, d2: int, vgpr_a: int, vgpr_b: int, lds_fused: int) -> int:
+    return lib().hf_register_bound(d1, d2, vgpr_a, vgpr_b, lds_fused)
+
+
+def hf_copy(dst, src, nbytes: int, stream=None, timed=False):
+    ms = _ms(timed)
+    _check(lib().hf_copy(_ptr(dst), _ptr(src), nbytes, _stream(stream),
+                         ctypes.byref(ms) if ms is not None else None), "hf_copy")
+    return ms.value if ms is not None else None
+
+
+def hf_scrub(stream=None):
+    _check(lib().hf_scrub(_stream(stream)), "hf_scrub")
+
+
+def hf_warmup(ms: int = 500, stream=None):
+    _check(lib().hf_warmup(ms, _stream(stream)), "hf_warmup")

@@ -38,7 +38,7 @@ def bn_input(shape, seed: int = 0) -> np.ndarray:
 def normal_image(shape, seed: int = 0) -> np.ndarray:
     g = rng(seed)
     x = np.empty(shape, np.float32)
-    flat = x.reshape(shape[0], -1)
+    flat = x.reshape(shape[0], int(np.prod(shape[1:])))
     for n in range(shape[0]):
         flat[n] = g.standard_normal(size=flat.shape[1], dtype=np.float32)
     return x

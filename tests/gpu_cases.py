@@ -1,0 +1,164 @@
+"""Seeded GPU test cases: device buffers for one task of each kind, plus the
+check of its outputs against the CPU oracle.
+
+Tolerances (written here, used by every GPU test):
+  * integer and copy kernels (int_mix, lds_hist, im2col): bit-exact;
+  * bn_stats: |d mean| <= 1e-5 * (|mean| + sigma) and |d var| <= 1e-5 * var
+    (a relative bound on the mean alone is ill-posed when the mean is ~0);
+  * upsample: |d out| <= 1e-5 * sum_k |w_k x_k| over the four taps.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+import oracle
+from paper_2007_01277_amd import hfuse as H
+from paper_2007_01277_amd import inputs
+
+DEV = "cuda"
+TOL = 1e-5
+
+
+def dev(a: np.ndarray, offset: int = 0) -> torch.Tensor:
+    """Device copy of `a`; with offset > 0 the tensor is a view that starts
+    `offset` elements into a larger allocation (misaligned for vector loads)."""
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if offset == 0:
+        return t.to(DEV)
+    flat = t.reshape(-1)
+    big = torch.zeros(flat.numel() + offset, dtype=flat.dtype, device=DEV)
+    big[offset:] = flat.to(DEV)
+    return big[offset:].view(a.shape)
+
+
+class Case:
+    """One task with its device buffers and host-side expected values."""
+
+    def __init__(self, task, bufs, check, label):
+        self.task, self.bufs, self.check, self.label = task, bufs, check, label
+
+    def outputs(self):
+        return [b.clone() for b in self.bufs["outs"]]
+
+    def reset(self):
+        for o in self.bufs["outs"]:
+            o.fill_(0xCD if o.dtype == torch.uint8 else 7)
+
+
+def bn_case(shape, seed=0, offset=0, x=None) -> Case:
+    xh = inputs.bn_input(shape, seed) if x is None else x
+    xd = dev(xh, offset)
+    C = shape[1]
+    mean = torch.full((C,), 7.0, device=DEV)
+    var = torch.full((C,), 7.0, device=DEV)
+    t = H.task_bn_stats(xd, mean, var)
+    ref = None
+
+    def check(outs, channels=None):
+        nonlocal ref
+        sel = np.arange(C) if channels is None else np.asarray(channels)
+        if ref is None or channels is not None:
+            m_ref, v_ref = oracle.bn_stats(xh[:, sel])
+            if channels is None:
+                ref = (m_ref, v_ref)
+        else:
+            m_ref, v_ref = ref
+        m = outs[0].cpu().numpy().astype(np.float64)[sel]
+        v = outs[1].cpu().numpy().astype(np.float64)[sel]
+        sd = np.sqrt(v_ref)
+        assert np.all(np.abs(m - m_ref) <= TOL * (np.abs(m_ref) + sd)), (m - m_ref, sd)
+        assert np.all(np.abs(v - v_ref) <= TOL * v_ref), (v - v_ref) / np.maximum(v_ref, 1e-300)
+
+    return Case(t, {"in": xd, "outs": [mean, var]}, check, f"bn_stats{tuple(shape)}+{offset}")
+
+
+def mix_case(n, rounds, seed=0, offset=0, sample=None) -> Case:
+    sh = inputs.uint32_seeds(n, seed)
+    sd = dev(sh.view(np.int32), offset)
+    out = dev(np.zeros(n, np.int32), offset)
+    t = H.task_int_mix(sd, out, rounds)
+
+    def check(outs):
+        got = outs[0].cpu().numpy().view(np.uint32)
+        if sample is None:
+            assert np.array_equal(got, oracle.int_mix(sh, rounds))
+        else:
+            idx = np.unique(np.concatenate([np.arange(min(n, 64)), np.arange(max(0, n - 64), n),
+                                            inputs.rng(seed + 7).integers(0, n, size=sample)]))
+            assert np.array_equal(got[idx], oracle.int_mix(sh[idx], rounds))
+
+    return Case(t, {"in": sd, "outs": [out]}, check, f"int_mix({n},{rounds})+{offset}")
+
+
+def hist_case(n, seed=0, offset=0, zipf=True) -> Case:
+    xh = inputs.zipf_u8(n, seed=seed) if zipf else inputs.uniform_u8(n, seed)
+    xd = dev(xh, offset)
+    counts = torch.full((256,), 12345, dtype=torch.int32, device=DEV)
+    t = H.task_lds_hist(xd, counts)
+
+    def check(outs):
+        got = outs[0].cpu().numpy().view(np.uint32).astype(np.uint64)
+        assert np.array_equal(got, oracle.hist256(xh))
+
+    return Case(t, {"in": xd, "outs": [counts]}, check, f"lds_hist({n})+{offset}")
+
+
+def im2col_case(shape, k=(3, 3), s=1, p=1, seed=0, check_images=None) -> Case:
+    xh = inputs.normal_image(shape, seed)
+    xd = dev(xh)
+    oshape, Ho, Wo = oracle.im2col_shape(*shape, k[0], k[1], s, p)
+    out = torch.full(oshape, 7.0, device=DEV)
+    t = H.task_im2col(xd, out, k[0], k[1], s, p)
+
+    def check(outs):
+        imgs = range(shape[0]) if check_images is None else check_images
+        for i in imgs:
+            ref = oracle.im2col(xh[i:i + 1], k[0], k[1], s, p)
+            assert np.array_equal(outs[0][i:i + 1].cpu().numpy(), ref), f"image {i}"
+
+    return Case(t, {"in": xd, "outs": [out]}, check, f"im2col{tuple(shape)}k{k}s{s}p{p}")
+
+
+def up_case(shape, scale=2, seed=0, check_slice=None) -> Case:
+    xh = inputs.normal_image(shape, seed)
+    xd = dev(xh)
+    N, C, Hh, W = shape
+    out = torch.full((N, C, Hh * scale, W * scale), 7.0, device=DEV)
+    t = H.task_upsample(xd, out, scale)
+
+    def check(outs):
+        sl = (slice(None), slice(None)) if check_slice is None else check_slice
+        xs = np.ascontiguousarray(xh[sl])
+        ref = oracle.upsample(xs, scale)
+        mag = oracle.upsample_absmag(xs, scale)
+        got = outs[0][sl].cpu().numpy().astype(np.float64)
+        err = np.abs(got - ref)
+        assert np.all(err <= TOL * mag), float(np.max(err / np.maximum(mag, 1e-300)))
+
+    return Case(t, {"in": xd, "outs": [out]}, check, f"upsample{tuple(shape)}x{scale}")
+
+
+def small_cases(kind, seed=0):
+    """Small cases of one kind covering several tiles and a ragged tail."""
+    if kind == H.HF_BN_STATS:
+        return [bn_case((8, 32, 16, 16), seed), bn_case((3, 5, 7, 9), seed), bn_case((2, 3, 40, 52), seed, offset=1)]
+    if kind == H.HF_INT_MIX:
+        return [mix_case(65536, 32, seed), mix_case(100_003, 7, seed), mix_case(1029, 5, seed, offset=1)]
+    if kind == H.HF_LDS_HIST:
+        return [hist_case(1 << 20, seed), hist_case(100_003, seed, offset=3), hist_case(50_000, seed, zipf=False)]
+    if kind == H.HF_IM2COL:
+        return [im2col_case((2, 8, 14, 16), seed=seed), im2col_case((2, 3, 9, 11), (3, 3), 2, 1, seed),
+                im2col_case((1, 4, 6, 7), (2, 3), 1, 0, seed)]
+    if kind == H.HF_UPSAMPLE:
+        return [up_case((2, 8, 16, 16), 2, seed), up_case((1, 3, 5, 7), 3, seed), up_case((2, 2, 9, 33), 2, seed)]
+    raise ValueError(kind)
+
+
+def run_and_check(run, cases):
+    for c in cases:
+        c.reset()
+    run()
+    torch.cuda.synchronize()
+    for c in cases:
+        c.check(c.outputs())

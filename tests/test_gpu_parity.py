@@ -1,0 +1,173 @@
+"""GPU parity: every kernel solo, every fused pair at every legal (split, block,
+VGPR bound) and the unfused baselines, against the CPU oracle and against each
+other.  All calls go through the C ABI (libhfuse.so)."""
+import itertools
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2007_01277_amd import hfuse as H
+from tests import gpu_cases as G
+
+pytestmark = pytest.mark.gpu
+
+KINDS = range(5)
+BLOCKS = (256, 512, 1024)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    assert torch.cuda.is_available()
+    H.hf_init()
+    yield
+
+
+@pytest.mark.parametrize("kind", KINDS, ids=H.KIND_NAMES)
+@pytest.mark.parametrize("block", BLOCKS)
+def test_solo_matches_oracle(kind, block):
+    for c in G.small_cases(kind, seed=block):
+        print(c.label, block, flush=True)
+        G.run_and_check(lambda: H.hf_run_solo(c.task, block), [c])
+
+
+@pytest.mark.parametrize("kind", KINDS, ids=H.KIND_NAMES)
+def test_solo_grid_independent(kind):
+    c = G.small_cases(kind, seed=3)[0]
+    outs = []
+    for grid in (1, 3, 64, 4096):
+        c.reset()
+        H.hf_run_solo(c.task, 256, grid)
+        torch.cuda.synchronize()
+        outs.append(c.outputs())
+    c.check(outs[0])
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert torch.equal(a, b)
+
+
+PAIRS = [(a, b) for a in KINDS for b in KINDS]
+
+
+@pytest.mark.parametrize("ka,kb", PAIRS, ids=[f"{H.KIND_NAMES[a]}+{H.KIND_NAMES[b]}" for a, b in PAIRS])
+def test_fused_bit_exact_vs_solo_all_configs(ka, kb):
+    """Fused output equals the solo output bit for bit for every split, block and
+    VGPR bound, and the solo output matches the oracle."""
+    ca = G.small_cases(ka, seed=11)[0]
+    cb = G.small_cases(kb, seed=12)[1]  # a different shape than ca when ka == kb
+    print(ca.label, cb.label, flush=True)
+    G.run_and_check(lambda: (H.hf_run_solo(ca.task, 256), H.hf_run_solo(cb.task, 512)), [ca, cb])
+    ref_a, ref_b = ca.outputs(), cb.outputs()
+    pr = H.make_pair(ca.task, cb.task)
+    for block in BLOCKS:
+        W = block // 64
+        for w1 in range(1, W):
+            for cap in H.CAPS:
+                ca.reset()
+                cb.reset()
+                H.hf_run_fused_cfg(pr, H.hf_config(w1, block, cap, 0))
+                torch.cuda.synchronize()
+                for r, o in zip(ref_a, ca.outputs()):
+                    assert torch.equal(r, o), (ca.label, block, w1, cap)
+                for r, o in zip(ref_b, cb.outputs()):
+                    assert torch.equal(r, o), (cb.label, block, w1, cap)
+
+
+@pytest.mark.parametrize("mode", [H.HF_SERIAL, H.HF_STREAMS])
+def test_unfused_modes_match_oracle(mode):
+    for ka, kb in [(0, 1), (2, 3), (4, 3), (1, 0)]:
+        ca = G.small_cases(ka, seed=21)[0]
+        cb = G.small_cases(kb, seed=22)[0]
+        pr = H.make_pair(ca.task, cb.task)
+        side = torch.cuda.Stream()
+        for s1 in (None, side):
+            G.run_and_check(lambda: H.hf_run_unfused(pr, 256, 1024, mode, None, s1), [ca, cb])
+
+
+def test_small_config_bn_stats_with_int_mix():
+    """bn_stats [8,32,16,16] with int_mix 65536 x 32 rounds, split 1/2, block 256:
+    fused, back-to-back and two-stream runs against the oracle."""
+    ca = G.bn_case((8, 32, 16, 16), seed=0)
+    cb = G.mix_case(65536, 32, seed=0)
+    pr = H.make_pair(ca.task, cb.task)
+    G.run_and_check(lambda: H.hf_run_fused(pr, 1, 2, 256), [ca, cb])
+    f = [o.clone() for o in ca.outputs() + cb.outputs()]
+    G.run_and_check(lambda: H.hf_run_unfused(pr, 256, 256, H.HF_SERIAL), [ca, cb])
+    u = ca.outputs() + cb.outputs()
+    for x, y in zip(f, u):
+        assert torch.equal(x, y)
+    G.run_and_check(lambda: H.hf_run_unfused(pr, 256, 256, H.HF_STREAMS), [ca, cb])
+
+
+def test_repeated_launches_leave_scratch_clean():
+    ca = G.bn_case((4, 16, 32, 32), seed=5)
+    cb = G.hist_case(300_001, seed=5, offset=1)
+    pr = H.make_pair(ca.task, cb.task)
+    first = None
+    for i in range(5):
+        G.run_and_check(lambda: H.hf_run_fused(pr, 3, 4, 512), [ca, cb])
+        outs = ca.outputs() + cb.outputs()
+        if first is None:
+            first = outs
+        for x, y in zip(first, outs):
+            assert torch.equal(x, y)
+
+
+def test_fused_grid_independent():
+    ca = G.bn_case((4, 8, 30, 28), seed=6)
+    cb = G.hist_case(777_777, seed=6)
+    pr = H.make_pair(ca.task, cb.task)
+    ref = None
+    for grid in (1, 2, 13, 500, 3000):
+        G.run_and_check(lambda: H.hf_run_fused_cfg(pr, H.hf_config(5, 1024, 0, grid)), [ca, cb])
+        outs = ca.outputs() + cb.outputs()
+        if ref is None:
+            ref = outs
+        for x, y in zip(ref, outs):
+            assert torch.equal(x, y)
+
+
+def test_caller_scratch_regions():
+    ca = G.bn_case((2, 6, 20, 20), seed=8)
+    cb = G.hist_case(65_537, seed=8)
+    sa = torch.zeros(H.hf_scratch_bytes(ca.task) // 4 + 64, dtype=torch.int32, device="cuda")
+    sb = torch.zeros(H.hf_scratch_bytes(cb.task) // 4 + 64, dtype=torch.int32, device="cuda")
+    ca.task.scratch = sa.data_ptr()
+    cb.task.scratch = sb.data_ptr()
+    pr = H.make_pair(ca.task, cb.task)
+    for _ in range(2):
+        G.run_and_check(lambda: H.hf_run_fused(pr, 1, 4, 256), [ca, cb])
+        assert int(sa.abs().sum()) == 0 and int(sb.abs().sum()) == 0  # left zero-filled
+
+
+def test_edge_cases():
+    # empty and tiny inputs, ragged tails, scalar paths
+    cases = [G.mix_case(0, 3), G.mix_case(1, 3), G.mix_case(5, 2, offset=1), G.hist_case(0),
+             G.hist_case(1, offset=5), G.hist_case(17, offset=15), G.bn_case((1, 1, 1, 1)),
+             G.bn_case((1, 2, 1, 3)), G.im2col_case((1, 1, 1, 1)), G.im2col_case((1, 1, 2, 3), (1, 1), 1, 0),
+             G.up_case((1, 1, 1, 1), 2), G.up_case((1, 1, 1, 5), 16), G.up_case((0, 3, 4, 4), 2)]
+    for c in cases:
+        print(c.label, flush=True)
+        G.run_and_check(lambda: H.hf_run_solo(c.task, 256), [c])
+    for ca, cb in itertools.combinations(cases[:8], 2):
+        pr = H.make_pair(ca.task, cb.task)
+        G.run_and_check(lambda: H.hf_run_fused(pr, 1, 2, 256), [ca, cb])
+
+
+def test_bn_constant_input_exact():
+    x = np.full((3, 4, 17, 12), 0.75, np.float32)
+    c = G.bn_case(x.shape, x=x)
+    for block in BLOCKS:
+        c.reset()
+        H.hf_run_solo(c.task, block)
+        torch.cuda.synchronize()
+        m, v = c.outputs()
+        assert torch.all(m == 0.75) and torch.all(v == 0.0)
+
+
+def test_hist_totals_equal_n():
+    c = G.hist_case(3_000_017, seed=9, offset=7)
+    other = G.mix_case(1 << 20, 16, seed=9)
+    pr = H.make_pair(other.task, c.task)
+    G.run_and_check(lambda: H.hf_run_fused(pr, 7, 8, 1024, 64), [c, other])
+    assert int(c.outputs()[0].to(torch.int64).sum()) == 3_000_017
