@@ -15,7 +15,6 @@ fused kernel and the CPU oracle's time for the same step.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -60,15 +59,6 @@ def copy_calibration(mib):
     return 0
 
 
-def csrc_hash():
-    h = hashlib.sha256()
-    d = os.path.join(ROOT, "paper_2007_01277_amd", "csrc")
-    for f in sorted(os.listdir(d)):
-        with open(os.path.join(d, f), "rb") as fh:
-            h.update(f.encode() + fh.read())
-    return h.hexdigest()[:16]
-
-
 def traffic_from_profiles(kernel_key, launches_per_step=1):
     """HBM bytes per launch from the committed counter summary, if it was taken
     on the current kernel sources; None otherwise."""
@@ -77,6 +67,7 @@ def traffic_from_profiles(kernel_key, launches_per_step=1):
         return None
     with open(p) as fh:
         d = json.load(fh)
+    from paper_2007_01277_amd.rocprof_summary import csrc_hash
     e = d.get(kernel_key)
     if not e or e.get("csrc_hash") != csrc_hash():
         return None

@@ -23,13 +23,13 @@ struct BnArgs {  // per-channel mean / biased variance of NCHW fp32
   const float* x;
   float* mean;
   float* var;
-  uint32_t* ctr;   // [C] chunk arrival counters (zero between launches)
-  uint32_t* part;  // [C][chunks][2] chunk (mean, M2) as float bits
+  uint32_t* ctr;   // [C] unit arrival counters (zero between launches)
+  uint32_t* part;  // [C][upc][2] per-unit (mean, M2) as float bits
   uint32_t C, HW, M, CHWm;  // M = N*HW elements per channel, CHWm = (C-1)*HW
-  uint32_t chunks;          // chunks per channel
-  uint32_t total;           // C * chunks
+  uint32_t upc;             // units per channel
+  uint32_t total;           // C * upc
   uint32_t vec;             // float4 path: HW % 4 == 0 and x 16-byte aligned
-  FastDiv div_hw, div_chunks;
+  FastDiv div_hw, div_upc;
 };
 
 struct MixArgs {  // R rounds of xorshift32 + multiply-add per uint32
@@ -107,32 +107,33 @@ __device__ __forceinline__ void wait_vmem() {
 // arrival, which on a multi-XCD part stalls every wave of the die.  The wave
 // that sees itself as the last arrival reads the published data only with
 // agent-scope atomic loads or RMWs issued after its counter RMW returned.
-__device__ __forceinline__ uint32_t arrive_after_coherent_stores(uint32_t* ctr) {
+__device__ __forceinline__ uint32_t arrive_after_coherent_stores(uint32_t* ctr, uint32_t n = 1u) {
   wait_vmem();
-  return __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_fetch_add(ctr, n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ================================================================== bn_stats
 // Statistics kernel of the normalisation example (Sec. II-C): per-channel mean
 // and variance of x[N][C][H][W].
 //
-// Work decomposition (independent of grid and interval size):
-//   unit  = 1024 consecutive elements of one channel's N*H*W sequence; one
-//           wavefront loads it (16 values per lane), and computes the unit's
-//           mean and M2 by two passes over registers with fixed-order wave sums;
-//   chunk = 4 consecutive units; the wavefront merges its units in order with
-//           Chan's pairwise update and publishes (mean, M2) of the chunk;
-//   the wavefront that publishes a channel's last chunk (arrival counter) merges
-//           the channel's chunks in double and writes mean[c], var[c].
+// Work decomposition (fixed by the shape, independent of grid and interval):
+//   unit = 1024 consecutive elements of one channel's N*H*W sequence.  One
+//          wavefront loads it (16 values per lane, the next unit already in
+//          flight), computes the unit's mean and M2 by two passes over registers
+//          with fixed-order wave sums, and publishes (mean, M2).
+//   Each wavefront of the launch owns a contiguous, balanced range of units;
+//   at the end of each channel segment of its range it adds the segment's unit
+//   count to the channel's arrival counter.  The wavefront that completes a
+//   channel merges its units' (count, mean, M2) in double, in unit order, with
+//   Chan's pairwise update, and writes mean[c] and var[c] = M2 / M.
+// The unit results and their merge order do not depend on which wavefront
+// computed a unit, so every grid and split gives the same bits.
 struct BnStats {
   static constexpr uint32_t kUnit = 1024;
-  static constexpr uint32_t kChunkUnits = 4;
-  static constexpr uint32_t kChunk = kUnit * kChunkUnits;
   static constexpr uint32_t lds_words(int) { return 0; }
 
-  // one unit: 16 values per lane, lane-major so every load is coalesced
   struct Regs {
-    float v[16];
+    float v[16];  // lane-major: every load instruction is coalesced
   };
 
   __device__ static __forceinline__ void load_unit(const BnArgs& a, uint32_t c, uint32_t ubase,
@@ -177,76 +178,106 @@ struct BnStats {
     const BnArgs& a = dt.bn;
     const uint32_t lane = lane_id();
     const uint32_t nw = p.nwg * p.nwaves;
-    for (uint32_t chunk = p.wg * p.nwaves + p.wave; chunk < a.total; chunk += nw) {
-      const uint32_t c = fdiv(chunk, a.div_chunks);
-      const uint32_t k = chunk - c * a.chunks;
-      const uint32_t ebeg = k * kChunk;
-      const uint32_t eend = min(a.M, ebeg + kChunk);
-      float cnt = 0.f, mean = 0.f, m2 = 0.f;
-      Regs cur, nxt;
-      load_unit(a, c, ebeg, lane, cur);
-      for (uint32_t ub = ebeg; ub < eend; ub += kUnit) {
-        const bool more = ub + kUnit < eend;
-        if (more) load_unit(a, c, ub + kUnit, lane, nxt);  // next unit in flight
-        const float nu = (float)min(kUnit, eend - ub);
-        float s = 0.f;
+    const uint32_t gw = p.wg * p.nwaves + p.wave;
+    const uint32_t q = a.total / nw, r = a.total - q * nw;
+    const uint32_t ubeg = gw * q + min(gw, r);
+    const uint32_t uend = ubeg + q + (gw < r ? 1u : 0u);
+    if (ubeg >= uend) return;
+    uint32_t c = fdiv(ubeg, a.div_upc);
+    uint32_t k = ubeg - c * a.upc;
+    uint32_t seg = ubeg;  // first unit of the current channel segment
+    Regs cur, nxt;
+    load_unit(a, c, k * kUnit, lane, cur);
+    for (uint32_t u = ubeg; u < uend; ++u) {
+      const bool more = u + 1u < uend;
+      const bool last_of_channel = k + 1u == a.upc;
+      const uint32_t c2 = last_of_channel ? c + 1u : c;
+      const uint32_t k2 = last_of_channel ? 0u : k + 1u;
+      if (more) load_unit(a, c2, k2 * kUnit, lane, nxt);  // next unit in flight
+      const uint32_t ub = k * kUnit;
+      const float nu = (float)min(kUnit, a.M - ub);
+      float s = 0.f;
 #pragma unroll
-        for (int t = 0; t < 16; ++t) s += cur.v[t];
-        const float mu = wave_sum(s) / nu;
-        float q = 0.f;
+      for (int t = 0; t < 16; ++t) s += cur.v[t];
+      const float mu = wave_sum(s) / nu;
+      float sq = 0.f;
 #pragma unroll
-        for (int t = 0; t < 16; ++t) {
-          const float d = valid(a, ub, lane, t) ? cur.v[t] - mu : 0.f;
-          q += d * d;
-        }
-        const float m2u = wave_sum(q);
-        // Chan et al. pairwise update of (cnt, mean, m2) with (nu, mu, m2u)
-        const float nab = cnt + nu;
-        const float delta = mu - mean;
-        mean = mean + delta * (nu / nab);
-        m2 = m2 + m2u + delta * delta * (cnt * nu / nab);
-        cnt = nab;
-        if (more) cur = nxt;
+      for (int t = 0; t < 16; ++t) {
+        const float d = valid(a, ub, lane, t) ? cur.v[t] - mu : 0.f;
+        sq += d * d;
       }
-      // publish the chunk, then count it
-      uint32_t old = 0;
+      const float m2 = wave_sum(sq);
       if (lane == 0) {
-        store_agent(a.part + 2u * chunk + 0u, __builtin_bit_cast(uint32_t, mean));
-        store_agent(a.part + 2u * chunk + 1u, __builtin_bit_cast(uint32_t, m2));
-        old = arrive_after_coherent_stores(a.ctr + c);
+        store_agent(a.part + 2u * u, __builtin_bit_cast(uint32_t, mu));
+        store_agent(a.part + 2u * u + 1u, __builtin_bit_cast(uint32_t, m2));
       }
-      old = uniform(old);
-      if (old == a.chunks - 1u) finish_channel(a, c, lane);
+      if (last_of_channel || !more) {
+        const uint32_t cnt = u + 1u - seg;
+        uint32_t old = 0;
+        if (lane == 0) old = arrive_after_coherent_stores(a.ctr + c, cnt);
+        old = uniform(old);
+        if (old + cnt == a.upc) finish_channel(a, c, lane);
+        seg = u + 1u;
+      }
+      c = c2;
+      k = k2;
+      if (more) cur = nxt;
     }
   }
 
-  // Merge the chunks of channel c in double: mean = sum n_k mean_k / M,
-  // M2 = sum (M2_k + n_k (mean_k - mean)^2), var = M2 / M.
+  // Chan et al. pairwise update of (n, mean, M2) with (nb, mb, m2b), in double.
+  __device__ static __forceinline__ void chan(double& n, double& m, double& m2, double nb, double mb,
+                                              double m2b) {
+    const double nab = n + nb;
+    const double d = mb - m;
+    m = m + d * (nb / nab);
+    m2 = m2 + m2b + d * d * (n * nb / nab);
+    n = nab;
+  }
+
+  // Merge the units of channel c: each lane merges units lane, lane+64, ... in
+  // order, then the 64 lane results are merged by a fixed butterfly.
   __device__ static void finish_channel(const BnArgs& a, uint32_t c, uint32_t lane) {
-    const uint32_t base = 2u * c * a.chunks;
-    double s = 0.0;
-    for (uint32_t k = lane; k < a.chunks; k += 64u) {
-      const double nk = (double)min(kChunk, a.M - k * kChunk);
-      s += nk * (double)__builtin_bit_cast(float, load_agent(a.part + base + 2u * k));
-    }
-    const double mu = wave_sum_f64(s) / (double)a.M;
-    double q = 0.0;
-    for (uint32_t k = lane; k < a.chunks; k += 64u) {
-      const double nk = (double)min(kChunk, a.M - k * kChunk);
+    const uint32_t base = 2u * c * a.upc;
+    double n = 0.0, m = 0.0, m2 = 0.0;
+    for (uint32_t k = lane; k < a.upc; k += 64u) {
+      const double nk = (double)min(kUnit, a.M - k * kUnit);
       const double mk = (double)__builtin_bit_cast(float, load_agent(a.part + base + 2u * k));
       const double m2k = (double)__builtin_bit_cast(float, load_agent(a.part + base + 2u * k + 1u));
-      const double d = mk - mu;
-      q += m2k + nk * d * d;
+      chan(n, m, m2, nk, mk, m2k);
     }
-    const double var = wave_sum_f64(q) / (double)a.M;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const double nb = __shfl_xor(n, off, kWave);
+      const double mb = __shfl_xor(m, off, kWave);
+      const double m2b = __shfl_xor(m2, off, kWave);
+      if (nb > 0.0) {
+        if (n > 0.0) {
+          // the lower lane of the pair is always the left operand
+          if ((lane & (uint32_t)off) == 0u) {
+            chan(n, m, m2, nb, mb, m2b);
+          } else {
+            double nl = nb, ml = mb, m2l = m2b;
+            chan(nl, ml, m2l, n, m, m2);
+            n = nl;
+            m = ml;
+            m2 = m2l;
+          }
+        } else {
+          n = nb;
+          m = mb;
+          m2 = m2b;
+        }
+      }
+    }
     // leave the scratch zero-filled, as every kernel of the library does
-    for (uint32_t k = lane; k < a.chunks; k += 64u) {
+    for (uint32_t k = lane; k < a.upc; k += 64u) {
       store_agent(a.part + base + 2u * k, 0u);
       store_agent(a.part + base + 2u * k + 1u, 0u);
     }
     if (lane == 0) {
-      a.mean[c] = (float)mu;
-      a.var[c] = (float)var;
+      a.mean[c] = (float)m;
+      a.var[c] = (float)(m2 / (double)a.M);
       store_agent(a.ctr + c, 0u);  // leave the counter zero for the next launch
     }
   }

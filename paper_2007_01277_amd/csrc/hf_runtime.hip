@@ -202,9 +202,9 @@ int validate_task(const hf_task* t) {
   return HF_EINVAL;
 }
 
-static uint32_t bn_chunks(const hf_task* t) {
+static uint32_t bn_units(const hf_task* t) {
   const int64_t M = t->n * t->h * t->w;
-  return (uint32_t)((M + BnStats::kChunk - 1) / BnStats::kChunk);
+  return (uint32_t)((M + BnStats::kUnit - 1) / BnStats::kUnit);
 }
 
 int64_t scratch_bytes(const hf_task* t) {
@@ -213,7 +213,7 @@ int64_t scratch_bytes(const hf_task* t) {
   switch (t->kind) {
     case HF_BN_STATS: {
       const int64_t ctr = (t->c + 63) / 64 * 64;  // counters, padded to 256 B
-      return 4 * (ctr + 2 * t->c * (int64_t)bn_chunks(t));
+      return 4 * (ctr + 2 * t->c * (int64_t)bn_units(t));
     }
     case HF_LDS_HIST:
       return 4 * (256 + 64);
@@ -238,11 +238,11 @@ int prepare(const hf_task* t, void* scratch, DevTask* dt) {
       a.HW = (uint32_t)(t->h * t->w);
       a.M = (uint32_t)(t->n * t->h * t->w);
       a.CHWm = (a.C - 1u) * a.HW;
-      a.chunks = bn_chunks(t);
-      a.total = a.C * a.chunks;
+      a.upc = bn_units(t);
+      a.total = a.C * a.upc;
       a.vec = (a.HW % 4u == 0u) && aligned(t->in, 16);
       a.div_hw = make_fastdiv(a.HW);
-      a.div_chunks = make_fastdiv(a.chunks);
+      a.div_upc = make_fastdiv(a.upc);
       return HF_OK;
     }
     case HF_INT_MIX: {

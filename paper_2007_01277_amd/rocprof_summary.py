@@ -1,0 +1,154 @@
+"""Turns rocprofv3 CSV output into the short summaries kept under profiles/.
+
+  python -m paper_2007_01277_amd.rocprof_summary stats  --csv DIR/trace_kernel_stats.csv --cmd "..." --out profiles/X.md
+  python -m paper_2007_01277_amd.rocprof_summary counters --dir DIR [--dir DIR ...] --match SUBSTR --cmd "..." --out profiles/Y.md
+  python -m paper_2007_01277_amd.rocprof_summary traffic --fetch DIR --write DIR --copy-fetch DIR --copy-write DIR
+         --copy-bytes B --match SUBSTR --key NAME --alg-bytes B --cmd "..." --out profiles/Z.md
+
+`traffic` scales the FETCH_SIZE / WRITE_SIZE counters (KiB per dispatch) of the
+matched kernel by what the same counters read for the library's copy kernel
+moving a known number of bytes, and records the result, with a hash of the
+kernel sources it was measured on, in profiles/traffic.json.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import hashlib
+import json
+import os
+import statistics
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def csrc_hash():
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2007_01277_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def short(name: str) -> str:
+    s = name.replace("hf::", "").replace("(DevTask, DevTask, unsigned int)", "").replace("(DevTask)", "")
+    return s if len(s) <= 90 else s[:87] + "..."
+
+
+def stats(a):
+    rows = list(csv.DictReader(open(a.csv)))
+    out = [f"# Kernel trace: {a.title}", "", f"Command (from the repository root):", "", "```", a.cmd, "```", "",
+           "| kernel | calls | avg us | min us | max us | % time |", "|---|---:|---:|---:|---:|---:|"]
+    for r in rows:
+        out.append(f"| `{short(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                   f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} |")
+    if a.note:
+        out += ["", a.note]
+    open(a.out, "w").write("\n".join(out) + "\n")
+
+
+def read_pmc(d):
+    """{kernel name: {counter: [values per dispatch]}} of one rocprofv3 --pmc output dir."""
+    res = {}
+    for root, _, files in os.walk(d):
+        for f in files:
+            if f.endswith("counter_collection.csv"):
+                for r in csv.DictReader(open(os.path.join(root, f))):
+                    res.setdefault(r["Kernel_Name"], {}).setdefault(r["Counter_Name"], []).append(
+                        float(r["Counter_Value"]))
+    return res
+
+
+def pick(res, match):
+    """Kernel names matching `match`: alternatives separated by '|', each a
+    list of substrings separated by '&' that must all occur."""
+    alts = [a.split("&") for a in match.split("|")]
+    names = [k for k in res if any(all(m in k for m in alt) for alt in alts)]
+    if not names:
+        raise SystemExit(f"no kernel matches {match!r}: {list(res)}")
+    return names
+
+
+def counters(a):
+    lines = [f"# Counters: {a.title}", "", "Commands (from the repository root), one rocprofv3 pass each:", "", "```"]
+    lines += a.cmd.split(";;")
+    lines += ["```", "", "| kernel | counter | dispatches | mean per dispatch |", "|---|---|---:|---:|"]
+    for d in a.dir:
+        res = read_pmc(d)
+        for n in pick(res, a.match):
+            for c, v in sorted(res[n].items()):
+                lines.append(f"| `{short(n)}` | {c} | {len(v)} | {statistics.mean(v):.3f} |")
+    if a.note:
+        lines += ["", a.note]
+    open(a.out, "w").write("\n".join(lines) + "\n")
+
+
+def traffic(a):
+    def mean_of(d, counter, match):
+        res = read_pmc(d)
+        names = pick(res, match)
+        vals = [v for n in names for v in res[n].get(counter, [])]
+        return statistics.mean(vals), len(vals), names
+
+    f_kib, nf, names = mean_of(a.fetch, "FETCH_SIZE", a.match)
+    w_kib, nw, _ = mean_of(a.write, "WRITE_SIZE", a.match)
+    cf_kib, _, _ = mean_of(a.copy_fetch, "FETCH_SIZE", "k_copy")
+    cw_kib, _, _ = mean_of(a.copy_write, "WRITE_SIZE", "k_copy")
+    sf = a.copy_bytes / (cf_kib * 1024.0)  # bytes per counted KiB, reads
+    sw = a.copy_bytes / (cw_kib * 1024.0)  # bytes per counted KiB, writes
+    rd = f_kib * 1024.0 * sf
+    wr = w_kib * 1024.0 * sw
+    entry = {"kernel": [short(n) for n in names], "fetch_kib": round(f_kib, 1), "write_kib": round(w_kib, 1),
+             "copy_scale_read": round(sf, 4), "copy_scale_write": round(sw, 4),
+             "hbm_read_bytes": round(rd), "hbm_write_bytes": round(wr),
+             "hbm_bytes_per_launch": round(rd + wr), "algorithmic_bytes": a.alg_bytes,
+             "traffic_over_algorithmic": round((rd + wr) / a.alg_bytes, 4) if a.alg_bytes else None,
+             "dispatches": [nf, nw], "csrc_hash": csrc_hash()}
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    data = json.load(open(path)) if os.path.exists(path) else {}
+    data[a.key] = entry
+    json.dump(data, open(path, "w"), indent=1, sort_keys=True)
+    lines = [f"# HBM traffic: {a.title}", "", "Commands (from the repository root), one rocprofv3 pass each:", "", "```"]
+    lines += a.cmd.split(";;")
+    lines += ["```", "",
+              f"Copy kernel reference: {a.copy_bytes} bytes read and written; FETCH_SIZE read {cf_kib:.1f} KiB "
+              f"(scale {sf:.4f}), WRITE_SIZE read {cw_kib:.1f} KiB (scale {sw:.4f}).", "",
+              "| quantity | value |", "|---|---:|",
+              f"| FETCH_SIZE per dispatch (KiB) | {f_kib:.1f} |", f"| WRITE_SIZE per dispatch (KiB) | {w_kib:.1f} |",
+              f"| HBM read per launch (scaled, bytes) | {rd:.4g} |", f"| HBM write per launch (scaled, bytes) | {wr:.4g} |",
+              f"| algorithmic bytes per launch | {a.alg_bytes:.4g} |",
+              f"| traffic / algorithmic | {(rd + wr) / a.alg_bytes:.3f} |" if a.alg_bytes else "",
+              "", f"Kernel sources hash: `{entry['csrc_hash']}` (the bench reports this traffic only while it matches)."]
+    open(a.out, "w").write("\n".join(lines) + "\n")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="mode", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("--csv", required=True)
+    for p in (s,):
+        p.add_argument("--cmd", required=True)
+        p.add_argument("--out", required=True)
+        p.add_argument("--title", default="")
+        p.add_argument("--note", default="")
+    c = sub.add_parser("counters")
+    c.add_argument("--dir", action="append", required=True)
+    c.add_argument("--match", required=True)
+    c.add_argument("--cmd", required=True)
+    c.add_argument("--out", required=True)
+    c.add_argument("--title", default="")
+    c.add_argument("--note", default="")
+    t = sub.add_parser("traffic")
+    for k in ("fetch", "write", "copy_fetch", "copy_write", "match", "key", "cmd", "out"):
+        t.add_argument("--" + k.replace("_", "-"), required=True)
+    t.add_argument("--copy-bytes", type=float, required=True)
+    t.add_argument("--alg-bytes", type=float, default=0.0)
+    t.add_argument("--title", default="")
+    a = ap.parse_args()
+    {"stats": stats, "counters": counters, "traffic": traffic}[a.mode](a)
+
+
+if __name__ == "__main__":
+    main()

@@ -124,10 +124,10 @@ def test_bad_hist_bins_and_upsample_scale():
 def test_scratch_bytes():
     assert H.hf_scratch_bytes(_mix()) == 0
     assert H.hf_scratch_bytes(_hist()) == 4 * 320
-    # bn: C counters padded to 64 words, then (mean, M2) per 4096-element chunk
+    # bn: C counters padded to 64 words, then (mean, M2) per 1024-element unit
     t = _bn(n=64, c=256, h=56, w=56)
-    chunks = -(-64 * 56 * 56 // 4096)
-    assert H.hf_scratch_bytes(t) == 4 * (256 + 2 * 256 * chunks)
+    units = -(-64 * 56 * 56 // 1024)
+    assert H.hf_scratch_bytes(t) == 4 * (256 + 2 * 256 * units)
     assert H.hf_scratch_bytes(_bn(n=0)) == H.HF_EINVAL
 
 
