@@ -1,0 +1,70 @@
+"""Parity at the full workload sizes, in the launch configurations the bench
+uses: fused output bit-exact with the back-to-back output over every element,
+and sampled outputs (channels, elements, images) against the CPU oracle."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2007_01277_amd import hfuse as H
+from tests import gpu_cases as G
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def bn_mix():
+    ca = G.bn_case((64, 256, 56, 56), seed=0)
+    cb = G.mix_case(1 << 24, 128, seed=0, sample=4096)
+    return ca, cb
+
+
+def _fused_vs_serial(ca, cb, cfg, blocks=(1024, 1024)):
+    pr = H.make_pair(ca.task, cb.task)
+    for c in (ca, cb):
+        c.reset()
+    H.hf_run_unfused(pr, blocks[0], blocks[1], H.HF_SERIAL)
+    torch.cuda.synchronize()
+    ref = ca.outputs() + cb.outputs()
+    for c in (ca, cb):
+        c.reset()
+    H.hf_run_fused_cfg(pr, H.hf_config(*cfg, 0))
+    torch.cuda.synchronize()
+    got = ca.outputs() + cb.outputs()
+    for r, g in zip(ref, got):
+        assert torch.equal(r, g), cfg
+    return got
+
+
+@pytest.mark.parametrize("cfg", [(1, 512, 64), (4, 1024, 0), (2, 256, 0), (14, 1024, 128), (7, 512, 80)])
+def test_bn_stats_int_mix_full_size(bn_mix, cfg):
+    ca, cb = bn_mix
+    print("bn_stats[64,256,56,56] + int_mix 2^24x128", cfg, flush=True)
+    outs = _fused_vs_serial(ca, cb, cfg)
+    chans = [0, 1, 17, 128, 200, 255]
+    ca.check(outs[:2], channels=chans)
+    cb.check(outs[2:])
+
+
+def test_im2col_hist_full_size():
+    ca = G.im2col_case((32, 128, 56, 56), seed=1, check_images=[0, 31])
+    cb = G.hist_case(1 << 26, seed=2)
+    for cfg in [(8, 1024, 128), (3, 512, 0), (2, 256, 64)]:
+        print("im2col[32,128,56,56] + lds_hist 2^26", cfg, flush=True)
+        outs = _fused_vs_serial(ca, cb, cfg)
+    ca.check(outs[:1])
+    cb.check(outs[1:])
+    assert int(outs[1].to(torch.int64).sum()) == 1 << 26
+
+
+def test_upsample_hist_full_size():
+    ca = G.up_case((32, 64, 128, 128), 2, seed=3, check_slice=(slice(0, 1), slice(0, 4)))
+    cb = G.hist_case(1 << 26, seed=2)
+    for cfg in [(4, 1024, 64), (5, 512, 0)]:
+        print("upsample[32,64,128,128]x2 + lds_hist 2^26", cfg, flush=True)
+        outs = _fused_vs_serial(ca, cb, cfg)
+    ca.check(outs[:1])
+    cb.check(outs[1:])
+    # the last image too
+    ca2 = G.up_case((32, 64, 128, 128), 2, seed=3, check_slice=(slice(31, 32), slice(60, 64)))
+    ca2.bufs = ca.bufs  # same seed, same bytes
+    ca2.check(outs[:1])
