@@ -230,6 +230,78 @@ int hf_tune_candidates(int method, int block, int vgpr_a, int vgpr_b, int lds_fu
  * bytes and the partition sizes.  Returns r0 (>= 1) or HF_EINVAL. */
 int hf_register_bound(int d1, int d2, int vgpr_a, int vgpr_b, int lds_fused);
 
+/* ---------------------------------------------------------------- learned cost model */
+/* A multilayer perceptron (three hidden layers of 64 ReLU units, linear output)
+ * that predicts log2 of a fused launch's time in ms from HF_MLP_FEATURES
+ * features: per kernel (a, then b) a one-hot kind, log2 solo time (best of the
+ * three block sizes), log2 algorithmic bytes and lane-ops, and the fractions of
+ * HBM and integer-ALU peak the solo run reached; then the split fraction, block
+ * size, VGPR bound, resident wavefronts per SIMD and four time estimates built
+ * from the solo times and the split.  Trained and evaluated on the GPU by the
+ * library's own kernels.  One model per process, on the device current at
+ * hf_mlp_init.  Unless stated otherwise, arrays are HOST pointers, row-major. */
+#define HF_MLP_FEATURES 28
+/* Allocates the model for d_in features: He-uniform weights from `seed`
+ * (splitmix64), zero biases, identity feature standardisation. */
+int hf_mlp_init(int d_in, uint64_t seed);
+/* Number of parameters of the current model, or HF_ENOMODEL. */
+int hf_mlp_num_params(void);
+/* Copies the flat parameter vector (layout W1[d][64] b1 W2[64][64] b2 W3 b3
+ * W4[64][1] b4) out of / into the model; n must equal hf_mlp_num_params(). */
+int hf_mlp_get_params(float* host, int64_t n);
+int hf_mlp_set_params(const float* host, int64_t n);
+/* Mean squared error and its gradient (same layout as the parameters) on
+ * already standardised X[n][d], y[n]; parameters are not changed. */
+int hf_mlp_grad(const float* X, const float* y, int n, float* loss_out, float* grad_out);
+/* One full-batch Adam step (lr, beta1 0.9, beta2 0.999, eps 1e-8) on already
+ * standardised data; loss_out (may be NULL) receives the loss before the step. */
+int hf_mlp_step(const float* X, const float* y, int n, float lr, float* loss_out);
+/* Zeroes Adam's moments and step count. */
+int hf_mlp_adam_reset(void);
+/* Standardises raw X[n][d] and y[n] with their own mean and deviation (kept in
+ * the model), resets Adam and runs `epochs` full-batch steps; loss_out (may be
+ * NULL) receives the standardised training loss after the last step. */
+int hf_mlp_train(const float* X, const float* y, int n, int d, int epochs, float lr, float* loss_out);
+/* Predictions for raw X[n][d] in the units of the training targets. */
+int hf_mlp_predict(const float* X, int n, float* y_out);
+/* Saves / loads the model (parameters and standardisation) to / from a file. */
+int hf_mlp_save(const char* path);
+int hf_mlp_load(const char* path);
+/* Features of `n` fused configurations of the pair.  Runs each task solo at the
+ * three block sizes to time it (overwriting the tasks' outputs) on `stream`. */
+int hf_featurize(const hf_pair* pr, const hf_config* cfg, int n, void* stream, float* X_out);
+
+/* ---------------------------------------------------------------- batched N-way fusion */
+/* Many small instances in ONE persistent launch.  Tasks are cut into groups
+ * (group_of_task[i]: nondecreasing ids, each group 1..4 consecutive tasks).
+ * Each group runs as an N-way horizontally fused virtual launch: a workgroup of
+ * `block` lanes (256, 512 or 1024) gives waves_of_task[i] wavefronts to task i
+ * (>= 1 each, at most block/64 per group; NULL = proportional to each task's
+ * estimated cost), every task runs its body on its own interval with its own
+ * interval barrier, and the persistent workgroups pull (group, virtual
+ * workgroup) items from a device queue.  Generalises the two-interval
+ * Generate algorithm of Sec. III-A to N intervals.
+ * hf_batch_create copies the task table to the device (tasks are read only
+ * during the call), allocates scratch for the tasks that need it and have none
+ * (zero-filled, left zero-filled by every launch), and returns an opaque handle
+ * for the current device.  hf_batch_run launches it on `stream`; with
+ * use_graph != 0 the launch is captured once into a HIP graph and the graph is
+ * replayed.  Runs of one batch must not overlap in time. */
+int hf_batch_create(const hf_task* tasks, int ntask, const int32_t* group_of_task,
+                    const int32_t* waves_of_task, int block, void** batch_out);
+int hf_batch_run(void* batch, int use_graph, void* stream, float* ms_out);
+/* Work items (virtual workgroups summed over groups), persistent grid, groups. */
+int hf_batch_info(void* batch, int32_t* total_items, int32_t* grid, int32_t* ngroup);
+int hf_batch_destroy(void* batch);
+/* create + run + synchronise + destroy. */
+int hf_run_batch(const hf_task* tasks, int ntask, const int32_t* group_of_task,
+                 const int32_t* waves_of_task, int block, void* stream, float* ms_out);
+/* Schedule tuner of a batch: profiles (median of `reps` launches) the cost-
+ * proportional and the even wave split at block 256 and 512; writes the best
+ * per-task waves (ntask entries) and block, and its median time. */
+int hf_batch_tune(const hf_task* tasks, int ntask, const int32_t* group_of_task, int reps, void* stream,
+                  int32_t* waves_out, int32_t* block_out, float* ms_out);
+
 /* ---------------------------------------------------------------- microbenchmarks */
 /* Streams `bytes` (multiple of 16) from src to dst: the reference copy kernel
  * for measured HBM ceilings and for scaling rocprof byte counters. */

@@ -32,7 +32,7 @@ def _units():
     units = []
     for a, b in PAIRS:
         units.append((os.path.join(CSRC, "hf_pairs.hip"), f"pair_{a}_{b}.o", [f"-DHF_KA={a}", f"-DHF_KB={b}"]))
-    for name in ("hf_solo", "hf_runtime", "hf_tune", "hf_mlp"):
+    for name in ("hf_solo", "hf_runtime", "hf_tune", "hf_mlp", "hf_batch"):
         units.append((os.path.join(CSRC, name + ".hip"), name + ".o", []))
     return units
 

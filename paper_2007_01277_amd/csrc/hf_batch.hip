@@ -1,0 +1,489 @@
+// hf_batch.hip -- many small kernel instances fused into one persistent launch.
+//
+// The paper fuses two kernels per launch; with many small, uneven instances the
+// launch overhead itself dominates (Sec. I, footnote on tiny kernels).  Here the
+// instances are cut into groups of two to four, and each group is executed as
+// an N-way horizontally fused "virtual launch": a workgroup's wavefronts are
+// split into one interval per member (the Generate algorithm with N bodies),
+// each member runs its own body on its own interval, with its own interval
+// barrier.  One persistent kernel executes every group: each resident
+// workgroup repeatedly pulls the next (group, virtual workgroup) item from a
+// device queue, so the items of one group run concurrently on many CUs and the
+// whole batch costs one launch, which can be captured in a HIP graph.
+//
+// Item boundaries are the only whole-workgroup barriers; every cross-workgroup
+// counter (queue, bn_stats units, histogram arrivals) is left at zero when the
+// launch ends, so the captured graph can be replayed without a memset.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+#include "hf_runtime.hpp"
+
+namespace hf {
+
+constexpr int kMaxMembers = 4;
+
+struct BatchTables {
+  const DevTask* tasks;        // [ntask]
+  const int32_t* kinds;        // [ntask]
+  const int32_t* wave0;        // [ntask] first wavefront of the task's interval
+  const int32_t* wave1;        // [ntask] one past its last wavefront
+  const int32_t* grp_first;    // [ngroup + 1] first task of each group
+  const uint32_t* item_start;  // [ngroup + 1] first item of each group
+  const uint32_t* grp_nwg;     // [ngroup] virtual workgroups of each group
+  uint32_t* queue;             // [1] pull counter, zero between launches
+  uint32_t ngroup;
+  uint32_t total_items;
+};
+
+template <class Bar>
+__device__ __forceinline__ void run_body(int kind, const DevTask& t, const Part& p, Bar& bar, uint32_t* lds) {
+  switch (kind) {
+    case HF_BN_STATS: BnStats::run(t, p, bar, lds); break;
+    case HF_INT_MIX: IntMix::run(t, p, bar, lds); break;
+    case HF_IM2COL: Im2col::run(t, p, bar, lds); break;
+    case HF_LDS_HIST: LdsHist::run(t, p, bar, lds); break;
+    case HF_UPSAMPLE: Upsample::run(t, p, bar, lds); break;
+    default: break;
+  }
+}
+
+template <int BLOCK>
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5))) k_batch(BatchTables T) {
+  __shared__ uint32_t smem[kMaxMembers + kMaxMembers * LdsHist::lds_words(BLOCK)];
+  __shared__ uint32_t item_sh[2];
+  const uint32_t wave = uniform(threadIdx.x >> 6);
+  if (threadIdx.x == 0)
+    item_sh[0] = __hip_atomic_fetch_add(T.queue, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (uint32_t it = 0;; it ^= 1u) {
+    if (threadIdx.x == 0)
+      for (int m = 0; m < kMaxMembers; ++m) smem[m] = 0u;
+    __syncthreads();
+    const uint32_t item = uniform(item_sh[it]);
+    if (item >= T.total_items) {
+      // the last pull of the launch resets the queue for the next launch
+      if (threadIdx.x == 0 && item == T.total_items + gridDim.x - 1u)
+        __hip_atomic_store(T.queue, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      break;
+    }
+    // the next item is pulled now; its latency hides behind this item's work
+    if (threadIdx.x == 0)
+      item_sh[it ^ 1u] = __hip_atomic_fetch_add(T.queue, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // group of the item: last g with item_start[g] <= item
+    uint32_t lo = 0, hi = T.ngroup;
+    while (hi - lo > 1u) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (T.item_start[mid] <= item) lo = mid;
+      else hi = mid;
+    }
+    const uint32_t g = lo;
+    const uint32_t b = item - T.item_start[g];
+    const int32_t t0 = T.grp_first[g], t1 = T.grp_first[g + 1];
+    int32_t mine = -1;
+    for (int32_t m = t0; m < t1; ++m)
+      if (wave >= (uint32_t)T.wave0[m] && wave < (uint32_t)T.wave1[m]) mine = m;
+    mine = (int32_t)uniform((uint32_t)mine);
+    if (mine >= 0) {
+      const uint32_t w0 = uniform((uint32_t)T.wave0[mine]), w1 = uniform((uint32_t)T.wave1[mine]);
+      const uint32_t nw = w1 - w0;
+      const Part p{threadIdx.x - 64u * w0, 64u * nw, wave - w0, nw, b, uniform(T.grp_nwg[g])};
+      PartBarrier bar(&smem[mine - t0], nw);
+      // the task's arguments are wave-uniform: keep them in scalar registers
+      DevTask dt;
+      const uint32_t* src = reinterpret_cast<const uint32_t*>(&T.tasks[mine]);
+      uint32_t* dst = reinterpret_cast<uint32_t*>(&dt);
+#pragma unroll
+      for (int i = 0; i < (int)(sizeof(DevTask) / 4); ++i) dst[i] = uniform(src[i]);
+      run_body((int)uniform((uint32_t)T.kinds[mine]), dt, p, bar,
+               &smem[kMaxMembers + (uint32_t)(mine - t0) * LdsHist::lds_words(BLOCK)]);
+    }
+    __syncthreads();  // item boundary: every interval has finished
+  }
+}
+
+// ------------------------------------------------------------------ host side
+struct Batch {
+  int device = 0, block = 256, ntask = 0, ngroup = 0;
+  uint32_t total_items = 0;
+  std::vector<hf_task> tasks;
+  void* dmem = nullptr;     // tables + queue
+  void* scratch = nullptr;  // per-task scratch regions
+  BatchTables tab{};
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t cap = nullptr;
+  int grid = 0;
+};
+
+static const void* batch_kernel(int block) {
+  switch (block) {
+    case 256: return reinterpret_cast<const void*>(&k_batch<256>);
+    case 512: return reinterpret_cast<const void*>(&k_batch<512>);
+    case 1024: return reinterpret_cast<const void*>(&k_batch<1024>);
+  }
+  return nullptr;
+}
+
+static double est_cost_us(const hf_task* t) {
+  const double n = (double)t->n, c = (double)t->c, h = (double)t->h, w = (double)t->w;
+  double bytes = 0, ops = 0;
+  switch (t->kind) {
+    case HF_BN_STATS: bytes = 4 * n * c * h * w; ops = 4 * n * c * h * w; break;
+    case HF_INT_MIX: bytes = 8 * n; ops = 8.0 * n * t->p[0]; break;
+    case HF_IM2COL: {
+      const double kk = (double)t->p[0] * t->p[1];
+      bytes = 4 * n * c * h * w * (1 + kk);
+      ops = 10 * n * c * h * w * kk;
+      break;
+    }
+    case HF_LDS_HIST: bytes = n; ops = 16 * n; break;  // LDS atomics, not HBM, bound this kernel
+    case HF_UPSAMPLE: {
+      const double s2 = (double)t->p[0] * t->p[0];
+      bytes = 4 * n * c * h * w * (1 + s2);
+      ops = 20 * n * c * h * w * s2;
+      break;
+    }
+  }
+  return std::max(bytes / 5.0e6, ops / 38.0e6);  // us at ~5 TB/s and ~38 T lane-op/s
+}
+
+// Waves of each task of a group: proportional to the estimated cost, at
+// least one each, summing to W.
+static void proportional_waves(const hf_task* t, int n, int W, int32_t* out) {
+  std::vector<double> c(n);
+  double tot = 0;
+  for (int i = 0; i < n; ++i) tot += (c[i] = std::max(est_cost_us(&t[i]), 1e-3));
+  int left = W;
+  for (int i = 0; i < n; ++i) {
+    out[i] = 1;
+    --left;
+  }
+  while (left > 0) {  // give each next wave to the member with the largest cost per wave
+    int best = 0;
+    for (int i = 1; i < n; ++i)
+      if (c[i] / out[i] > c[best] / out[best]) best = i;
+    ++out[best];
+    --left;
+  }
+  (void)tot;
+}
+
+static int batch_free(Batch* B) {
+  if (!B) return HF_OK;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(B->device);
+  (void)hipDeviceSynchronize();
+  if (B->exec) (void)hipGraphExecDestroy(B->exec);
+  if (B->graph) (void)hipGraphDestroy(B->graph);
+  if (B->cap) (void)hipStreamDestroy(B->cap);
+  if (B->dmem) (void)hipFree(B->dmem);
+  if (B->scratch) (void)hipFree(B->scratch);
+  delete B;
+  (void)hipSetDevice(cur);
+  return HF_OK;
+}
+
+static int batch_launch(Batch* B, hipStream_t st) {
+  void* args[] = {&B->tab};
+  hipError_t e = hipLaunchKernel(batch_kernel(B->block), dim3(B->grid), dim3(B->block), args, 0, st);
+  return e == hipSuccess ? HF_OK : record_hip(e);
+}
+
+static int batch_create(const hf_task* tasks, int ntask, const int32_t* group_of_task,
+                        const int32_t* waves_of_task, int block, Batch** out) {
+  if (!tasks || ntask < 1 || !group_of_task || !out) return HF_EINVAL;
+  if (check_block(block) != HF_OK) return HF_EINVAL;
+  const int W = block / 64;
+  int rc;
+  // groups: consecutive runs of equal ids, ids nondecreasing, 1..4 members
+  std::vector<int32_t> first{0};
+  for (int i = 0; i < ntask; ++i) {
+    if ((rc = validate_task(&tasks[i])) != HF_OK) return rc;
+    if (i > 0 && group_of_task[i] != group_of_task[i - 1]) {
+      if (group_of_task[i] < group_of_task[i - 1]) return HF_EINVAL;
+      first.push_back(i);
+    }
+  }
+  first.push_back(ntask);
+  const int ngroup = (int)first.size() - 1;
+  std::vector<int32_t> waves(ntask), w0(ntask), w1(ntask);
+  for (int g = 0; g < ngroup; ++g) {
+    const int n = first[g + 1] - first[g];
+    if (n > kMaxMembers || n > W) return HF_EINVAL;
+    if (waves_of_task) {
+      int sum = 0;
+      for (int i = first[g]; i < first[g + 1]; ++i) {
+        if (waves_of_task[i] < 1) return HF_EINVAL;
+        sum += waves_of_task[i];
+        waves[i] = waves_of_task[i];
+      }
+      if (sum > W) return HF_EINVAL;
+    } else {
+      proportional_waves(&tasks[first[g]], n, W, &waves[first[g]]);
+    }
+    int w = 0;
+    for (int i = first[g]; i < first[g + 1]; ++i) {
+      w0[i] = w;
+      w += waves[i];
+      w1[i] = w;
+    }
+  }
+  DeviceState* s = device_state(&rc);
+  if (!s) return rc;
+  Batch* B = new Batch();
+  B->device = s->device;
+  B->block = block;
+  B->ntask = ntask;
+  B->ngroup = ngroup;
+  B->tasks.assign(tasks, tasks + ntask);
+  // scratch: one 256-byte aligned region per task that needs it
+  std::vector<size_t> soff(ntask, 0);
+  size_t sbytes = 0;
+  for (int i = 0; i < ntask; ++i) {
+    const int64_t nb = scratch_bytes(&tasks[i]);
+    if (nb > 0 && !tasks[i].scratch) {
+      soff[i] = sbytes;
+      sbytes += ((size_t)nb + 255) & ~size_t(255);
+    }
+  }
+  hipError_t e;
+  if (sbytes > 0) {
+    if ((e = hipMalloc(&B->scratch, sbytes)) != hipSuccess) {
+      batch_free(B);
+      record_hip(e);
+      return HF_ENOMEM;
+    }
+    if ((e = hipMemset(B->scratch, 0, sbytes)) != hipSuccess) {
+      batch_free(B);
+      return record_hip(e);
+    }
+  }
+  // device task arguments and virtual workgroups per group
+  const char* ikb = std::getenv("HF_BATCH_ITEM_KB");
+  const double item_bytes = 1024.0 * std::max(1, ikb ? std::atoi(ikb) : 256);
+  std::vector<DevTask> dts(ntask);
+  std::vector<int32_t> kinds(ntask);
+  std::vector<uint32_t> nwg(ngroup), istart(ngroup + 1, 0);
+  for (int g = 0; g < ngroup; ++g) {
+    int64_t need = 1;
+    double bytes = 0;
+    for (int i = first[g]; i < first[g + 1]; ++i) {
+      void* scr = tasks[i].scratch ? tasks[i].scratch
+                                   : (scratch_bytes(&tasks[i]) > 0 ? (char*)B->scratch + soff[i] : nullptr);
+      if ((rc = prepare(&tasks[i], scr, &dts[i])) != HF_OK) {
+        batch_free(B);
+        return rc;
+      }
+      kinds[i] = tasks[i].kind;
+      need = std::max(need, useful_wgs(&tasks[i], dts[i], waves[i]));
+      bytes += est_cost_us(&tasks[i]) * 5.0e6;
+    }
+    // enough virtual workgroups for every member's units, but items of about
+    // item_bytes of traffic, so that the per-item barriers stay cheap
+    const int64_t by_bytes = std::max<int64_t>(1, (int64_t)(bytes / item_bytes));
+    nwg[g] = (uint32_t)std::max<int64_t>(1, std::min<int64_t>(need, by_bytes));
+    istart[g + 1] = istart[g] + nwg[g];
+  }
+  B->total_items = istart[ngroup];
+  // one device allocation for every table
+  auto al = [](size_t v) { return (v + 255) & ~size_t(255); };
+  const size_t o_tasks = 0, o_kinds = al(o_tasks + sizeof(DevTask) * ntask),
+               o_w0 = al(o_kinds + 4 * ntask), o_w1 = al(o_w0 + 4 * ntask), o_first = al(o_w1 + 4 * ntask),
+               o_istart = al(o_first + 4 * (ngroup + 1)), o_nwg = al(o_istart + 4 * (ngroup + 1)),
+               o_queue = al(o_nwg + 4 * ngroup), total = al(o_queue + 4);
+  if ((e = hipMalloc(&B->dmem, total)) != hipSuccess) {
+    batch_free(B);
+    record_hip(e);
+    return HF_ENOMEM;
+  }
+  std::vector<char> host(total, 0);
+  std::memcpy(host.data() + o_tasks, dts.data(), sizeof(DevTask) * ntask);
+  std::memcpy(host.data() + o_kinds, kinds.data(), 4 * ntask);
+  std::memcpy(host.data() + o_w0, w0.data(), 4 * ntask);
+  std::memcpy(host.data() + o_w1, w1.data(), 4 * ntask);
+  std::memcpy(host.data() + o_first, first.data(), 4 * (ngroup + 1));
+  std::memcpy(host.data() + o_istart, istart.data(), 4 * (ngroup + 1));
+  std::memcpy(host.data() + o_nwg, nwg.data(), 4 * ngroup);
+  if ((e = hipMemcpy(B->dmem, host.data(), total, hipMemcpyHostToDevice)) != hipSuccess) {
+    batch_free(B);
+    return record_hip(e);
+  }
+  char* d = static_cast<char*>(B->dmem);
+  B->tab.tasks = reinterpret_cast<const DevTask*>(d + o_tasks);
+  B->tab.kinds = reinterpret_cast<const int32_t*>(d + o_kinds);
+  B->tab.wave0 = reinterpret_cast<const int32_t*>(d + o_w0);
+  B->tab.wave1 = reinterpret_cast<const int32_t*>(d + o_w1);
+  B->tab.grp_first = reinterpret_cast<const int32_t*>(d + o_first);
+  B->tab.item_start = reinterpret_cast<const uint32_t*>(d + o_istart);
+  B->tab.grp_nwg = reinterpret_cast<const uint32_t*>(d + o_nwg);
+  B->tab.queue = reinterpret_cast<uint32_t*>(d + o_queue);
+  B->tab.ngroup = (uint32_t)ngroup;
+  B->tab.total_items = B->total_items;
+  const int g = occupancy_grid(s, batch_kernel(block), block, nullptr);
+  if (g < 0) {
+    batch_free(B);
+    return g;
+  }
+  B->grid = (int)std::max<int64_t>(1, std::min<int64_t>(g, B->total_items));
+  *out = B;
+  return HF_OK;
+}
+
+static int batch_run(Batch* B, int use_graph, hipStream_t st) {
+  if (!use_graph) return batch_launch(B, st);
+  hipError_t e;
+  if (!B->exec) {
+    if (!B->cap && (e = hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking)) != hipSuccess)
+      return record_hip(e);
+    if ((e = hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal)) != hipSuccess) return record_hip(e);
+    int rc = batch_launch(B, B->cap);
+    hipGraph_t gr = nullptr;
+    e = hipStreamEndCapture(B->cap, &gr);
+    if (rc != HF_OK) return rc;
+    if (e != hipSuccess) return record_hip(e);
+    B->graph = gr;
+    if ((e = hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0)) != hipSuccess) return record_hip(e);
+  }
+  e = hipGraphLaunch(B->exec, st);
+  return e == hipSuccess ? HF_OK : record_hip(e);
+}
+
+static int batch_time(Batch* B, int use_graph, hipStream_t st, float* ms) {
+  int rc;
+  DeviceState* s = device_state(&rc);
+  if (!s) return rc;
+  if (ms) {
+    hipError_t e = hipEventRecord(s->ev_start, st);
+    if (e != hipSuccess) return record_hip(e);
+  }
+  if ((rc = batch_run(B, use_graph, st)) != HF_OK) return rc;
+  if (!ms) return HF_OK;
+  hipError_t e = hipEventRecord(s->ev_stop, st);
+  if (e != hipSuccess) return record_hip(e);
+  if ((rc = wait_event(s->ev_stop)) != HF_OK) return rc;
+  e = hipEventElapsedTime(ms, s->ev_start, s->ev_stop);
+  return e == hipSuccess ? HF_OK : record_hip(e);
+}
+
+static int check_batch(void* b, Batch** out) {
+  if (!b) return HF_EINVAL;
+  Batch* B = static_cast<Batch*>(b);
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return record_hip(e);
+  if (dev != B->device) return HF_EINVAL;
+  *out = B;
+  return HF_OK;
+}
+
+}  // namespace hf
+
+using namespace hf;
+
+extern "C" {
+
+int hf_batch_create(const hf_task* tasks, int ntask, const int32_t* group_of_task,
+                    const int32_t* waves_of_task, int block, void** batch_out) {
+  if (!batch_out) return HF_EINVAL;
+  *batch_out = nullptr;
+  Batch* B = nullptr;
+  int rc = batch_create(tasks, ntask, group_of_task, waves_of_task, block, &B);
+  if (rc == HF_OK) *batch_out = B;
+  return rc;
+}
+
+int hf_batch_run(void* batch, int use_graph, void* stream, float* ms_out) {
+  Batch* B = nullptr;
+  int rc = check_batch(batch, &B);
+  if (rc != HF_OK) return rc;
+  return batch_time(B, use_graph, static_cast<hipStream_t>(stream), ms_out);
+}
+
+int hf_batch_info(void* batch, int32_t* total_items, int32_t* grid, int32_t* ngroup) {
+  Batch* B = nullptr;
+  int rc = check_batch(batch, &B);
+  if (rc != HF_OK) return rc;
+  if (total_items) *total_items = (int32_t)B->total_items;
+  if (grid) *grid = B->grid;
+  if (ngroup) *ngroup = B->ngroup;
+  return HF_OK;
+}
+
+int hf_batch_destroy(void* batch) { return batch_free(static_cast<Batch*>(batch)); }
+
+int hf_run_batch(const hf_task* tasks, int ntask, const int32_t* group_of_task,
+                 const int32_t* waves_of_task, int block, void* stream, float* ms_out) {
+  void* b = nullptr;
+  int rc = hf_batch_create(tasks, ntask, group_of_task, waves_of_task, block, &b);
+  if (rc != HF_OK) return rc;
+  rc = hf_batch_run(b, 0, stream, ms_out);
+  if (rc == HF_OK && !ms_out) {
+    hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));  // before freeing the tables
+    if (e != hipSuccess) rc = record_hip(e);
+  }
+  hf_batch_destroy(b);
+  return rc;
+}
+
+// The batch schedule tuner: profiles the batch under two split policies
+// (proportional to the estimated cost, and even) at workgroup sizes 256 and
+// 512, and returns the fastest schedule's per-task waves and block.
+int hf_batch_tune(const hf_task* tasks, int ntask, const int32_t* group_of_task, int reps, void* stream,
+                  int32_t* waves_out, int32_t* block_out, float* ms_out) {
+  if (!tasks || ntask < 1 || !group_of_task || !waves_out || !block_out || reps < 1) return HF_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  float best = 1e30f;
+  const int blocks[] = {256, 512};
+  for (int block : blocks) {
+    const int W = block / 64;
+    for (int policy = 0; policy < 2; ++policy) {
+      std::vector<int32_t> waves(ntask);
+      int i = 0;
+      bool ok = true;
+      while (i < ntask) {
+        int j = i;
+        while (j < ntask && group_of_task[j] == group_of_task[i]) ++j;
+        const int n = j - i;
+        if (n > W || n > kMaxMembers) {
+          ok = false;
+          break;
+        }
+        if (policy == 0) proportional_waves(&tasks[i], n, W, &waves[i]);
+        else
+          for (int k = 0; k < n; ++k) waves[i + k] = W / n + (k < W % n ? 1 : 0);
+        i = j;
+      }
+      if (!ok) continue;
+      void* b = nullptr;
+      int rc = hf_batch_create(tasks, ntask, group_of_task, waves.data(), block, &b);
+      if (rc != HF_OK) return rc;
+      std::vector<float> ts;
+      for (int r = 0; r <= reps; ++r) {
+        float ms = 0.f;
+        if ((rc = hf_batch_run(b, 0, st, &ms)) != HF_OK) {
+          hf_batch_destroy(b);
+          return rc;
+        }
+        if (r > 0) ts.push_back(ms);
+      }
+      hf_batch_destroy(b);
+      std::sort(ts.begin(), ts.end());
+      const float med = ts[ts.size() / 2];
+      if (med < best) {
+        best = med;
+        std::copy(waves.begin(), waves.end(), waves_out);
+        *block_out = block;
+      }
+    }
+  }
+  if (best >= 1e30f) return HF_EINVAL;
+  if (ms_out) *ms_out = best;
+  return HF_OK;
+}
+
+}  // extern "C"

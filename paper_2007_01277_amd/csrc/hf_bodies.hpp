@@ -53,11 +53,11 @@ struct HistArgs {  // 256-bin histogram of bytes
 struct Im2colArgs {  // patches -> columns, [N][C*kh*kw][Ho*Wo]
   const float* x;
   float* out;
-  uint32_t C, H, W, kw, s, p, Ho, Wo, KK, CKK;
-  uint32_t units;           // N * C * Ho: one unit = (n, c, oh) -> kh*kw output rows
-  uint32_t lanes_per_unit;  // KK * Wo4 (vector) or KK * Wo (scalar)
+  uint32_t C, H, W, kw, s, p, Ho, Wo, KK;
+  uint32_t units;           // N * C * kh*kw output planes
+  uint32_t lanes_per_unit;  // Ho * Wo4 (vector) or Ho * Wo (scalar)
   uint32_t vec;             // Wo % 4 == 0 and out 16-byte aligned
-  FastDiv div_ho, div_c, div_row, div_kw;  // div_row: by Wo4 (vector) or Wo
+  FastDiv div_kk, div_row, div_kw;  // div_row: by Wo4 (vector) or Wo
 };
 
 struct UpArgs {  // bilinear upsampling by integer factor s, half-pixel centres
@@ -324,32 +324,36 @@ struct IntMix {
 
 // ================================================================== lds_hist
 // Histogram kernel of Sec. II-C: clear shared-memory bins, count with shared-
-// memory atomics, merge the bins into the global counts.  Each wavefront owns
-// one copy of the 256 bins in LDS, so atomics of different wavefronts never
-// collide; the interval's barriers separate clearing, counting and merging.
-// The workgroups add their bins into an agent-scope accumulator; the last
-// workgroup to arrive moves the totals to the output and re-zeroes it.
+// memory atomics, merge the bins into the global counts.  The interval keeps
+// kCopies copies of the 256 bins in LDS, interleaved so that bin b of copy k is
+// word b*kCopies + k, and lane l counts into copy l % kCopies: lanes of one
+// instruction that see the same (frequent) value hit different words in
+// different banks instead of serialising on one address.  The interval's
+// barriers separate clearing, counting and merging.  Workgroups add their bins
+// into an agent-scope accumulator; the last workgroup to arrive moves the
+// totals to the output with atomic exchanges, which also re-zero it.
 struct LdsHist {
-  static constexpr uint32_t lds_words(int block) { return (uint32_t)(block / 64) * 256u; }
+  static constexpr uint32_t kCopies = 8;
+  static constexpr uint32_t lds_words(int) { return 256u * kCopies; }
 
-  __device__ static __forceinline__ void count_byte(uint32_t* bins, uint32_t b) {
-    __hip_atomic_fetch_add(bins + b, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  __device__ static __forceinline__ void count_byte(uint32_t* mine, uint32_t b) {
+    __hip_atomic_fetch_add(mine + b * kCopies, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   }
-  __device__ static __forceinline__ void count_word(uint32_t* bins, uint32_t w) {
-    count_byte(bins, w & 0xFFu);
-    count_byte(bins, (w >> 8) & 0xFFu);
-    count_byte(bins, (w >> 16) & 0xFFu);
-    count_byte(bins, w >> 24);
+  __device__ static __forceinline__ void count_word(uint32_t* mine, uint32_t w) {
+    count_byte(mine, w & 0xFFu);
+    count_byte(mine, (w >> 8) & 0xFFu);
+    count_byte(mine, (w >> 16) & 0xFFu);
+    count_byte(mine, w >> 24);
   }
 
   template <class Bar>
   __device__ static void run(const DevTask& dt, const Part& p, Bar& bar, uint32_t* lds) {
     const HistArgs& a = dt.hist;
     const uint32_t lane = lane_id();
-    for (uint32_t i = p.lane; i < p.nwaves * 256u; i += p.nlanes) lds[i] = 0u;
+    for (uint32_t i = p.lane; i < 256u * kCopies; i += p.nlanes) lds[i] = 0u;
     bar.sync();
 
-    uint32_t* mine = lds + p.wave * 256u;
+    uint32_t* mine = lds + (lane % kCopies);
     const uint32_t gl = p.wg * p.nlanes + p.lane;
     const uint32_t stride = p.nwg * p.nlanes;
     const uint4* v16 = reinterpret_cast<const uint4*>(a.in + a.head);
@@ -366,7 +370,8 @@ struct LdsHist {
 
     for (uint32_t b = p.lane; b < 256u; b += p.nlanes) {
       uint32_t s = 0;
-      for (uint32_t w = 0; w < p.nwaves; ++w) s += lds[w * 256u + b];
+#pragma unroll
+      for (uint32_t k = 0; k < kCopies; ++k) s += lds[b * kCopies + k];
       if (s) __hip_atomic_fetch_add(a.acc + b, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     wait_vmem();  // this wave's merge atomics have completed ...
@@ -387,8 +392,11 @@ struct LdsHist {
 
 // ================================================================== im2col
 // Im2Col (Sec. IV-A): out[n][(c*kh + i)*kw + j][oh*Wo + ow] = x[n][c][oh*s-p+i][ow*s-p+j],
-// zero outside the image.  A unit is one (n, c, oh): its kh*kw output row
-// segments of length Wo, written as float4 when Wo % 4 == 0.
+// zero outside the image.  A unit is one output plane (n, c*kh*kw + kk): Ho*Wo
+// contiguous floats, written front to back (float4 when Wo % 4 == 0), so every
+// store instruction covers whole aligned cache lines.  Kernel offsets kk are the
+// fastest-varying unit index, so the kh*kw planes that read one input plane run
+// next to each other and find it in cache.
 struct Im2col {
   static constexpr uint32_t lds_words(int) { return 0; }
 
@@ -398,23 +406,20 @@ struct Im2col {
     const uint32_t lane = lane_id();
     const uint32_t nw = p.nwg * p.nwaves;
     const uint32_t HW = a.H * a.W;
+    const uint32_t plane = a.Ho * a.Wo;
     for (uint32_t u = p.wg * p.nwaves + p.wave; u < a.units; u += nw) {
-      const uint32_t nc = fdiv(u, a.div_ho);
-      const uint32_t oh = u - nc * a.Ho;
-      const uint32_t n = fdiv(nc, a.div_c);
-      const uint32_t c = nc - n * a.C;
+      const uint32_t nc = fdiv(u, a.div_kk);  // n*C + c
+      const uint32_t kk = u - nc * a.KK;
+      const uint32_t i = fdiv(kk, a.div_kw);
+      const uint32_t j = kk - i * a.kw;
       const float* img = a.x + nc * HW;
-      float* obase = a.out + ((n * a.CKK + c * a.KK) * a.Ho + oh) * a.Wo;
-      const uint32_t rowstride = a.Ho * a.Wo;  // between consecutive kernel offsets
+      float* dst = a.out + u * plane;  // plane u = (n, c*KK + kk)
       for (uint32_t t = lane; t < a.lanes_per_unit; t += 64u) {
-        const uint32_t kk = fdiv(t, a.div_row);
-        const uint32_t col = t - kk * a.div_row.d;  // ow4 (vector) or ow (scalar)
-        const uint32_t i = fdiv(kk, a.div_kw);
-        const uint32_t j = kk - i * a.kw;
+        const uint32_t oh = fdiv(t, a.div_row);
+        const uint32_t col = t - oh * a.div_row.d;  // ow4 (vector) or ow (scalar)
         const int ih = (int)(oh * a.s + i) - (int)a.p;
         const bool rowok = ih >= 0 && ih < (int)a.H;
         const float* src = img + (rowok ? ih : 0) * (int)a.W;
-        float* dst = obase + kk * rowstride;
         if (a.vec) {
           float v[4];
 #pragma unroll
@@ -422,10 +427,11 @@ struct Im2col {
             const int iw = (int)((4u * col + e) * a.s + j) - (int)a.p;
             v[e] = (rowok && iw >= 0 && iw < (int)a.W) ? src[iw] : 0.f;
           }
-          *reinterpret_cast<float4*>(dst + 4u * col) = make_float4(v[0], v[1], v[2], v[3]);
+          store_nt4(dst + oh * a.Wo + 4u * col, v[0], v[1], v[2], v[3]);
         } else {
           const int iw = (int)(col * a.s + j) - (int)a.p;
-          dst[col] = (rowok && iw >= 0 && iw < (int)a.W) ? src[iw] : 0.f;
+          __builtin_nontemporal_store((rowok && iw >= 0 && iw < (int)a.W) ? src[iw] : 0.f,
+                                      dst + oh * a.Wo + col);
         }
       }
     }

@@ -36,6 +36,16 @@ __device__ __forceinline__ uint32_t uniform(uint32_t v) {
   return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
 }
 
+// ----------------------------------------------------------------- streaming stores
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// 16-byte store with the non-temporal hint: output that is written once and
+// not read back by the kernel should not displace inputs from the caches.
+__device__ __forceinline__ void store_nt4(float* p, float a, float b, float c, float d) {
+  f32x4 v = {a, b, c, d};
+  __builtin_nontemporal_store(v, reinterpret_cast<f32x4*>(p));
+}
+
 // ----------------------------------------------------------------- barriers
 struct WGBarrier {
   __device__ __forceinline__ void sync() { __syncthreads(); }

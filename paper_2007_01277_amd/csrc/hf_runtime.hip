@@ -98,6 +98,7 @@ DeviceState* device_state(int* status) {
 }
 
 void shutdown_all() {
+  mlp_free();
   std::lock_guard<std::mutex> lk(g_mu);
   int cur = 0;
   (void)hipGetDevice(&cur);
@@ -281,13 +282,11 @@ int prepare(const hf_task* t, void* scratch, DevTask* dt) {
       a.Ho = (a.H + 2 * p - kh) / s + 1;
       a.Wo = (a.W + 2 * p - kw) / s + 1;
       a.KK = kh * kw;
-      a.CKK = a.C * a.KK;
-      a.units = (uint32_t)t->n * a.C * a.Ho;
+      a.units = (uint32_t)t->n * a.C * a.KK;
       a.vec = (a.Wo % 4u == 0u) && aligned(t->out0, 16);
       const uint32_t rowlen = a.vec ? a.Wo / 4u : a.Wo;
-      a.lanes_per_unit = a.KK * rowlen;
-      a.div_ho = make_fastdiv(a.Ho);
-      a.div_c = make_fastdiv(a.C);
+      a.lanes_per_unit = a.Ho * rowlen;
+      a.div_kk = make_fastdiv(a.KK);
       a.div_row = make_fastdiv(rowlen);
       a.div_kw = make_fastdiv(kw);
       return HF_OK;

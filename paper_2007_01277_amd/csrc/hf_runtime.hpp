@@ -41,5 +41,8 @@ int launch_unfused(DeviceState* s, const hf_pair* pr, int block_a, int block_b, 
                    hipStream_t s0, hipStream_t s1);
 int wait_event(hipEvent_t ev);
 int kernel_info(DeviceState* s, const void* fn, int block, hf_kernel_info* out);
+void mlp_free();
+int64_t useful_wgs(const hf_task* t, const DevTask& d, int waves);
+int occupancy_grid(DeviceState* s, const void* fn, int block, int* wg_per_cu);
 
 }  // namespace hf

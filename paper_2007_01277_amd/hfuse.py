@@ -69,6 +69,7 @@ class hf_tune_stats(ctypes.Structure):
 _P = ctypes.c_void_p
 _I = ctypes.c_int
 _F = ctypes.POINTER(ctypes.c_float)
+_I32P = ctypes.POINTER(ctypes.c_int32)
 
 # name -> (restype, argtypes); the exported surface of include/hfuse.h
 SIGNATURES = {
@@ -91,6 +92,24 @@ SIGNATURES = {
     "hf_tune": (_I, [ctypes.POINTER(hf_pair), _I, _I, _I, _P, ctypes.POINTER(hf_config),
                      ctypes.POINTER(hf_tune_stats)]),
     "hf_register_bound": (_I, [_I, _I, _I, _I, _I]),
+    "hf_mlp_init": (_I, [_I, ctypes.c_uint64]),
+    "hf_mlp_num_params": (_I, []),
+    "hf_mlp_get_params": (_I, [_F, ctypes.c_int64]),
+    "hf_mlp_set_params": (_I, [_F, ctypes.c_int64]),
+    "hf_mlp_grad": (_I, [_F, _F, _I, _F, _F]),
+    "hf_mlp_step": (_I, [_F, _F, _I, ctypes.c_float, _F]),
+    "hf_mlp_adam_reset": (_I, []),
+    "hf_mlp_train": (_I, [_F, _F, _I, _I, _I, ctypes.c_float, _F]),
+    "hf_mlp_predict": (_I, [_F, _I, _F]),
+    "hf_mlp_save": (_I, [ctypes.c_char_p]),
+    "hf_mlp_load": (_I, [ctypes.c_char_p]),
+    "hf_featurize": (_I, [ctypes.POINTER(hf_pair), ctypes.POINTER(hf_config), _I, _P, _F]),
+    "hf_batch_create": (_I, [ctypes.POINTER(hf_task), _I, _I32P, _I32P, _I, ctypes.POINTER(_P)]),
+    "hf_batch_run": (_I, [_P, _I, _P, _F]),
+    "hf_batch_info": (_I, [_P, _I32P, _I32P, _I32P]),
+    "hf_batch_destroy": (_I, [_P]),
+    "hf_run_batch": (_I, [ctypes.POINTER(hf_task), _I, _I32P, _I32P, _I, _P, _F]),
+    "hf_batch_tune": (_I, [ctypes.POINTER(hf_task), _I, _I32P, _I, _P, _I32P, _I32P, _F]),
     "hf_copy": (_I, [_P, _P, ctypes.c_int64, _P, _F]),
     "hf_scrub": (_I, [_P]),
     "hf_warmup": (_I, [_I, _P]),
@@ -281,6 +300,156 @@ def hf_tune(pr: hf_pair, method: int = HF_TUNE_EXHAUSTIVE, block: int = 0, topk:
 
 def hf_register_bound(d1: int, d2: int, vgpr_a: int, vgpr_b: int, lds_fused: int) -> int:
     return lib().hf_register_bound(d1, d2, vgpr_a, vgpr_b, lds_fused)
+
+
+# ------------------------------------------------------------------ learned cost model
+MLP_FEATURES = 28
+
+
+def _f32(a):
+    import numpy as np
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    return a, a.ctypes.data_as(_F)
+
+
+def hf_mlp_init(d_in: int = MLP_FEATURES, seed: int = 0):
+    _check(lib().hf_mlp_init(d_in, seed), "hf_mlp_init")
+
+
+def hf_mlp_num_params() -> int:
+    return _check(lib().hf_mlp_num_params(), "hf_mlp_num_params")
+
+
+def hf_mlp_get_params():
+    import numpy as np
+    p = np.empty(hf_mlp_num_params(), np.float32)
+    _check(lib().hf_mlp_get_params(p.ctypes.data_as(_F), p.size), "hf_mlp_get_params")
+    return p
+
+
+def hf_mlp_set_params(p):
+    a, ptr = _f32(p)
+    _check(lib().hf_mlp_set_params(ptr, a.size), "hf_mlp_set_params")
+
+
+def hf_mlp_grad(X, y):
+    import numpy as np
+    Xa, xp = _f32(X)
+    ya, yp = _f32(y)
+    loss = ctypes.c_float(0.0)
+    g = np.empty(hf_mlp_num_params(), np.float32)
+    _check(lib().hf_mlp_grad(xp, yp, ya.size, ctypes.byref(loss), g.ctypes.data_as(_F)), "hf_mlp_grad")
+    return loss.value, g
+
+
+def hf_mlp_step(X, y, lr: float):
+    Xa, xp = _f32(X)
+    ya, yp = _f32(y)
+    loss = ctypes.c_float(0.0)
+    _check(lib().hf_mlp_step(xp, yp, ya.size, lr, ctypes.byref(loss)), "hf_mlp_step")
+    return loss.value
+
+
+def hf_mlp_adam_reset():
+    _check(lib().hf_mlp_adam_reset(), "hf_mlp_adam_reset")
+
+
+def hf_mlp_train(X, y, epochs: int = 2000, lr: float = 1e-3) -> float:
+    Xa, xp = _f32(X)
+    ya, yp = _f32(y)
+    loss = ctypes.c_float(0.0)
+    _check(lib().hf_mlp_train(xp, yp, ya.size, Xa.shape[1], epochs, lr, ctypes.byref(loss)), "hf_mlp_train")
+    return loss.value
+
+
+def hf_mlp_predict(X):
+    import numpy as np
+    Xa, xp = _f32(X)
+    y = np.empty(Xa.shape[0], np.float32)
+    _check(lib().hf_mlp_predict(xp, Xa.shape[0], y.ctypes.data_as(_F)), "hf_mlp_predict")
+    return y
+
+
+def hf_mlp_save(path: str):
+    _check(lib().hf_mlp_save(path.encode()), "hf_mlp_save")
+
+
+def hf_mlp_load(path: str):
+    _check(lib().hf_mlp_load(path.encode()), "hf_mlp_load")
+
+
+def hf_featurize(pr: hf_pair, cfgs, stream=None):
+    import numpy as np
+    arr = (hf_config * len(cfgs))(*cfgs)
+    X = np.empty((len(cfgs), MLP_FEATURES), np.float32)
+    _check(lib().hf_featurize(ctypes.byref(pr), arr, len(cfgs), _stream(stream), X.ctypes.data_as(_F)),
+           "hf_featurize")
+    return X
+
+
+# ------------------------------------------------------------------ batched N-way fusion
+def _i32(a):
+    if a is None:
+        return None, None
+    arr = (ctypes.c_int32 * len(a))(*[int(v) for v in a])
+    return arr, ctypes.cast(arr, _I32P)
+
+
+class Batch:
+    """Owns an hf_batch handle; keep the tasks' tensors alive while it is used."""
+
+    def __init__(self, tasks, groups, waves=None, block=256):
+        self.ntask = len(tasks)
+        self._tasks = (hf_task * len(tasks))(*tasks)
+        g_arr, g_ptr = _i32(groups)
+        w_arr, w_ptr = _i32(waves)
+        h = _P()
+        _check(lib().hf_batch_create(self._tasks, len(tasks), g_ptr, w_ptr, block, ctypes.byref(h)),
+               "hf_batch_create")
+        self.handle = h
+
+    def run(self, use_graph=False, stream=None, timed=False):
+        ms = _ms(timed)
+        _check(lib().hf_batch_run(self.handle, int(bool(use_graph)), _stream(stream),
+                                  ctypes.byref(ms) if ms is not None else None), "hf_batch_run")
+        return ms.value if ms is not None else None
+
+    def info(self):
+        a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().hf_batch_info(self.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)), "hf_batch_info")
+        return {"items": a.value, "grid": b.value, "groups": c.value}
+
+    def close(self):
+        if self.handle:
+            lib().hf_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def hf_run_batch(tasks, groups, waves=None, block=256, stream=None, timed=False):
+    arr = (hf_task * len(tasks))(*tasks)
+    g_arr, g_ptr = _i32(groups)
+    w_arr, w_ptr = _i32(waves)
+    ms = _ms(timed)
+    _check(lib().hf_run_batch(arr, len(tasks), g_ptr, w_ptr, block, _stream(stream),
+                              ctypes.byref(ms) if ms is not None else None), "hf_run_batch")
+    return ms.value if ms is not None else None
+
+
+def hf_batch_tune(tasks, groups, reps=5, stream=None):
+    arr = (hf_task * len(tasks))(*tasks)
+    g_arr, g_ptr = _i32(groups)
+    w_out = (ctypes.c_int32 * len(tasks))()
+    b_out = ctypes.c_int32()
+    ms = ctypes.c_float()
+    _check(lib().hf_batch_tune(arr, len(tasks), g_ptr, reps, _stream(stream), ctypes.cast(w_out, _I32P),
+                               ctypes.byref(b_out), ctypes.byref(ms)), "hf_batch_tune")
+    return list(w_out), b_out.value, ms.value
 
 
 def hf_copy(dst, src, nbytes: int, stream=None, timed=False):

@@ -68,3 +68,32 @@ def zipf_u8(n: int, s: float = 1.2, seed: int = 0, chunk: int = 1 << 22) -> np.n
 
 def uniform_u8(n: int, seed: int = 0) -> np.ndarray:
     return rng(seed).integers(0, 256, size=n, dtype=np.uint8)
+
+
+# ------------------------------------------------------------------ on-device generators
+# Seeded draws made directly on the GPU (torch's Philox generator) for large
+# timing workloads; the same distributions as above, different streams of
+# numbers.  Tests copy the device values back to the host before checking them
+# against the oracle.
+def cuda_generator(seed: int):
+    import torch
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    return g
+
+
+def cuda_normal(shape, seed: int):
+    import torch
+    return torch.randn(shape, generator=cuda_generator(seed), device="cuda")
+
+
+def cuda_uint32(n: int, seed: int):
+    import torch
+    return torch.randint(-2**31, 2**31 - 1, (n,), generator=cuda_generator(seed), device="cuda", dtype=torch.int32)
+
+
+def cuda_zipf_u8(n: int, seed: int, s: float = 1.2):
+    import torch
+    cdf = torch.from_numpy(zipf_cdf(s)).to("cuda")
+    u = torch.rand(n, generator=cuda_generator(seed), device="cuda", dtype=torch.float64)
+    return torch.clamp(torch.searchsorted(cdf, u, right=True), max=255).to(torch.uint8)

@@ -1,0 +1,200 @@
+"""Learned tuner: sample collection, training and regret against the exhaustive search.
+
+Workload: random pairs of two distinct kinds drawn from the five kernels, each
+of 2^k elements with k uniform in [16, 26] (image kinds as [2^k / 65536, 64, 32,
+32], integer mixing with 32 rounds, histogram bytes from the Zipf law).  For
+every pair the tuner's own profiler times every candidate of the exhaustive
+search (median of ``reps`` launches), and ``hf_featurize`` gives the model's
+features.  Cross-validation is by pair: the model is trained on a random subset
+of ~50 configurations of each training pair and judged on the held-out pairs,
+where it ranks all candidates and only the top k are "profiled" (their measured
+times are looked up).  Regret = T(choice) / T(exhaustive best) - 1.
+
+Baselines without the network: the even split at block 1024 without a bound
+("naive", Sec. IV-A), the even split with the register bound r0 of Sec. III-B
+("r0"), and k candidates drawn at random.
+
+    python -m paper_2007_01277_amd.learned_tuner --pairs 40 --out gpurun_out/tuner.json
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import sys
+import time
+
+import numpy as np
+
+from . import hfuse as H
+from . import inputs
+
+IMAGE = (64, 32, 32)  # C, H, W of the image kinds: 65536 elements per batch entry
+
+
+def draw_pairs(n_pairs: int, seed: int = 2, kmin: int = 16, kmax: int = 26):
+    g = inputs.rng(seed)
+    out = []
+    for _ in range(n_pairs):
+        a, b = g.choice(5, size=2, replace=False)
+        ka, kb = g.integers(kmin, kmax + 1, size=2)
+        out.append((int(a), int(b), int(ka), int(kb)))
+    return out
+
+
+class Instance:
+    """Device buffers of one task of `kind` with 2^k elements (values only
+    shape the timing; they are drawn on the GPU from a seeded generator)."""
+
+    def __init__(self, kind: int, k: int, seed: int):
+        import torch
+        n = 1 << k
+        self.bufs = []
+        if kind in (H.HF_BN_STATS, H.HF_IM2COL, H.HF_UPSAMPLE):
+            N = n // 65536
+            x = inputs.cuda_normal((N,) + IMAGE, seed)
+            self.bufs.append(x)
+            if kind == H.HF_BN_STATS:
+                m, v = torch.empty(IMAGE[0], device="cuda"), torch.empty(IMAGE[0], device="cuda")
+                self.bufs += [m, v]
+                self.task = H.task_bn_stats(x, m, v)
+            elif kind == H.HF_IM2COL:
+                o = torch.empty((N, IMAGE[0] * 9, IMAGE[1] * IMAGE[2]), device="cuda")
+                self.bufs.append(o)
+                self.task = H.task_im2col(x, o, 3, 3, 1, 1)
+            else:
+                o = torch.empty((N, IMAGE[0], 2 * IMAGE[1], 2 * IMAGE[2]), device="cuda")
+                self.bufs.append(o)
+                self.task = H.task_upsample(x, o, 2)
+        elif kind == H.HF_INT_MIX:
+            s = inputs.cuda_uint32(n, seed)
+            o = torch.empty_like(s)
+            self.bufs += [s, o]
+            self.task = H.task_int_mix(s, o, 32)
+        else:
+            x = inputs.cuda_zipf_u8(n, seed)
+            o = torch.empty(256, dtype=torch.int32, device="cuda")
+            self.bufs += [x, o]
+            self.task = H.task_lds_hist(x, o)
+
+
+def r0_config(kind_a: int, kind_b: int) -> H.hf_config:
+    """Even split of a 1024-lane workgroup with the register bound r0."""
+    va = H.hf_solo_info(kind_a, 1024)["vgprs"]
+    vb = H.hf_solo_info(kind_b, 1024)["vgprs"]
+    lds = H.hf_fused_info(kind_a, kind_b, 1024, 0)["lds_bytes"]
+    r0 = H.hf_register_bound(512, 512, va, vb, lds)
+    cap = max([c for c in (64, 80, 96, 128) if c <= r0] or [64])
+    return H.hf_config(8, 1024, cap, 0)
+
+
+def collect(pairs, reps: int = 10, seed: int = 2, log=sys.stderr):
+    """Profiles every exhaustive candidate of every pair; returns a dict of
+    numpy arrays (features X, log2 times y, pair index, candidate index)."""
+    import torch
+    cands = H.hf_tune_candidates(H.HF_TUNE_EXHAUSTIVE, 0)
+    keys = [c.as_tuple() for c in cands]
+    Xs, ys, pid, cid = [], [], [], []
+    t0 = time.time()
+    for p, (ka, kb, ea, eb) in enumerate(pairs):
+        ia = Instance(ka, ea, seed * 1000 + 2 * p)
+        ib = Instance(kb, eb, seed * 1000 + 2 * p + 1)
+        pr = H.make_pair(ia.task, ib.task)
+        X = H.hf_featurize(pr, cands)
+        y = np.array([math.log2(H.hf_profile(pr, c, reps)) for c in cands])
+        Xs.append(X)
+        ys.append(y)
+        pid += [p] * len(cands)
+        cid += list(range(len(cands)))
+        print(f"pair {p} {H.KIND_NAMES[ka]}(2^{ea}) + {H.KIND_NAMES[kb]}(2^{eb}): best {2 ** y.min():.4f} ms "
+              f"at {keys[int(np.argmin(y))]}  [{time.time() - t0:.1f}s]", file=log, flush=True)
+        del ia, ib, pr
+        torch.cuda.empty_cache()
+    return {"X": np.concatenate(Xs), "y": np.concatenate(ys), "pair": np.array(pid), "cand": np.array(cid),
+            "cands": keys, "pairs": pairs}
+
+
+def evaluate(data, folds: int = 4, per_pair: int = 50, topk: int = 3, epochs: int = 2000,
+             lr: float = 1e-3, seed: int = 7):
+    X, y, pair, cand = data["X"], data["y"], data["pair"], data["cand"]
+    keys = data["cands"]
+    npairs = int(pair.max()) + 1
+    g = inputs.rng(seed)
+    order = g.permutation(npairs)
+    naive = keys.index((8, 1024, 0, 0))
+    res = {"per_pair": [], "folds": folds, "topk": topk, "per_pair_train": per_pair, "epochs": epochs,
+           "n_candidates": len(keys)}
+    train_loss = []
+    for f in range(folds):
+        test = set(order[f::folds].tolist())
+        tr = [i for i in range(len(y)) if pair[i] not in test]
+        # ~per_pair random configurations of each training pair
+        keep = []
+        for p in sorted(set(pair[tr].tolist())):
+            idx = [i for i in tr if pair[i] == p]
+            keep += g.choice(idx, size=min(per_pair, len(idx)), replace=False).tolist()
+        keep = np.array(sorted(keep))
+        H.hf_mlp_init(X.shape[1], seed + f)
+        train_loss.append(H.hf_mlp_train(X[keep], y[keep], epochs=epochs, lr=lr))
+        for p in sorted(test):
+            idx = np.where(pair == p)[0]
+            ty = y[idx]
+            pred = H.hf_mlp_predict(X[idx])
+            top = np.argsort(pred, kind="stable")[:topk]
+            best = ty.min()
+            ka, kb = data["pairs"][p][0], data["pairs"][p][1]
+            r0 = r0_config(ka, kb).as_tuple()
+            rnd = g.choice(len(idx), size=topk, replace=False)
+            rec = {"pair": p, "kinds": [H.KIND_NAMES[ka], H.KIND_NAMES[kb]],
+                   "log2_sizes": list(data["pairs"][p][2:]),
+                   "best_ms": float(2 ** best),
+                   "regret_mlp": float(2 ** (ty[top].min() - best) - 1),
+                   "regret_naive": float(2 ** (ty[naive] - best) - 1),
+                   "regret_r0": float(2 ** (ty[keys.index(r0)] - best) - 1),
+                   "regret_random": float(2 ** (ty[rnd].min() - best) - 1),
+                   "rank_corr": float(np.corrcoef(np.argsort(np.argsort(pred)), np.argsort(np.argsort(ty)))[0, 1]),
+                   "pred_rmse_log2": float(np.sqrt(np.mean((pred - ty) ** 2)))}
+            res["per_pair"].append(rec)
+    pp = res["per_pair"]
+    for k in ("regret_mlp", "regret_naive", "regret_r0", "regret_random", "rank_corr", "pred_rmse_log2"):
+        v = np.array([r[k] for r in pp])
+        res[k + "_mean"] = float(v.mean())
+        res[k + "_max"] = float(v.max())
+    res["within_5pct_mlp"] = float(np.mean([r["regret_mlp"] <= 0.05 for r in pp]))
+    res["profiled_fraction"] = topk / len(keys)
+    res["train_loss"] = [float(v) for v in train_loss]
+    res["n_samples"] = int(len(y))
+    return res
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--pairs", type=int, default=40)
+    ap.add_argument("--kmin", type=int, default=16)
+    ap.add_argument("--kmax", type=int, default=26)
+    ap.add_argument("--reps", type=int, default=10)
+    ap.add_argument("--folds", type=int, default=4)
+    ap.add_argument("--topk", type=int, default=3)
+    ap.add_argument("--epochs", type=int, default=2000)
+    ap.add_argument("--out", default="")
+    ap.add_argument("--save-samples", default="")
+    a = ap.parse_args(argv)
+    import torch
+    torch.cuda.set_device(0)
+    H.hf_init()
+    H.hf_warmup(300)
+    pairs = draw_pairs(a.pairs, kmin=a.kmin, kmax=a.kmax)
+    data = collect(pairs, reps=a.reps)
+    if a.save_samples:
+        np.savez(a.save_samples, X=data["X"], y=data["y"], pair=data["pair"], cand=data["cand"],
+                 cands=np.array(data["cands"]), pairs=np.array(pairs))
+    res = evaluate(data, folds=a.folds, topk=a.topk, epochs=a.epochs)
+    summary = {k: v for k, v in res.items() if k != "per_pair"}
+    print(json.dumps(summary), flush=True)
+    if a.out:
+        json.dump(res, open(a.out, "w"), indent=1)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

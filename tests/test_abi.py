@@ -176,3 +176,21 @@ def test_exhaustive_candidates_are_wave_aligned_eighths():
         [(1024, 2 * k) for k in range(1, 8)]
     assert len(c) == 17 * len(H.CAPS)
     assert H.hf_tune_candidates(H.HF_TUNE_NAIVE, 0)[0].as_tuple() == (8, 1024, 0, 0)
+
+
+def test_batch_create_rejects_bad_groups_before_the_gpu():
+    L = H.lib()
+    tasks = (H.hf_task * 6)(*[_mix() for _ in range(6)])
+    h = ctypes.c_void_p()
+
+    def call(groups, waves, block=256):
+        g = (ctypes.c_int32 * 6)(*groups)
+        w = None if waves is None else ctypes.cast((ctypes.c_int32 * 6)(*waves), ctypes.POINTER(ctypes.c_int32))
+        return L.hf_batch_create(tasks, 6, ctypes.cast(g, ctypes.POINTER(ctypes.c_int32)), w, block,
+                                 ctypes.byref(h))
+
+    assert call([0, 0, 0, 0, 0, 1], None) == H.HF_EINVAL         # five members
+    assert call([0, 0, 1, 1, 0, 0], None) == H.HF_EINVAL         # ids go back
+    assert call([0, 0, 1, 1, 2, 2], [2, 3, 1, 1, 1, 1]) == H.HF_EINVAL  # 5 waves > 4
+    assert call([0, 0, 1, 1, 2, 2], [0, 1, 1, 1, 1, 1]) == H.HF_EINVAL  # a task without waves
+    assert call([0, 0, 1, 1, 2, 2], None, block=384) == H.HF_EINVAL

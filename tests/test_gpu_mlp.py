@@ -1,0 +1,127 @@
+"""The learned cost model on the GPU against its fp64 reference, and the tuner
+that uses it.
+
+Tolerances: the forward pass within 1e-5 of the magnitude of its terms (the
+same network evaluated on |W|, |b| and |x|, which bounds every partial sum);
+gradients within 1e-4 relative to the largest gradient of their layer plus
+1e-4 relative elementwise (fp32 sums over n = 2000 samples); one Adam step
+within 1e-6 absolute on every parameter whose gradient is not tiny.
+Several-step trajectories are not compared: fp32 and fp64 drift apart
+(parity unpinned beyond one step).
+"""
+import os
+import tempfile
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import mlp as ref
+from paper_2007_01277_amd import hfuse as H
+from paper_2007_01277_amd import inputs
+from paper_2007_01277_amd import learned_tuner as LT
+
+pytestmark = pytest.mark.gpu
+D = H.MLP_FEATURES
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _init():
+    assert torch.cuda.is_available()
+    H.hf_init()
+
+
+def _data(n, seed):
+    g = inputs.rng(seed)
+    X = g.standard_normal((n, D)).astype(np.float32)
+    y = (np.sin(X[:, 0]) + 0.5 * X[:, 1] * X[:, 2] + 0.1 * g.standard_normal(n)).astype(np.float32)
+    return X, y
+
+
+def _abs_forward(p, X):
+    layers = ref.unpack(np.abs(p.astype(np.float64)), X.shape[1])
+    h = np.abs(X.astype(np.float64))
+    for W, b in layers:
+        h = h @ W + b
+    return h[:, 0]
+
+
+def test_forward_matches_reference():
+    H.hf_mlp_init(D, 1)
+    p = H.hf_mlp_get_params()
+    assert p.size == ref.n_params(D)
+    X, _ = _data(333, 2)
+    got = H.hf_mlp_predict(X).astype(np.float64)
+    want, _ = ref.forward(p.astype(np.float64), X)
+    assert np.all(np.abs(got - want) <= 1e-5 * _abs_forward(p, X))
+
+
+def test_gradient_matches_reference():
+    H.hf_mlp_init(D, 3)
+    p = H.hf_mlp_get_params().astype(np.float64)
+    X, y = _data(2000, 4)
+    loss, g = H.hf_mlp_grad(X, y)
+    rl, rg = ref.grad(p, X, y)
+    assert abs(loss - rl) <= 1e-5 * rl
+    o = 0
+    for a, b in ref.layer_shapes(D):
+        for size in (a * b, b):
+            gs, rs = g[o:o + size].astype(np.float64), rg[o:o + size]
+            assert np.all(np.abs(gs - rs) <= 1e-4 * np.abs(rs) + 1e-4 * np.abs(rs).max()), o
+            o += size
+    assert o == g.size
+
+
+def test_adam_step_matches_reference():
+    H.hf_mlp_init(D, 5)
+    H.hf_mlp_adam_reset()
+    p = H.hf_mlp_get_params().astype(np.float64)
+    X, y = _data(500, 6)
+    H.hf_mlp_step(X, y, 1e-3)
+    p1 = H.hf_mlp_get_params().astype(np.float64)
+    _, rg = ref.grad(p, X, y)
+    rp, _, _ = ref.adam_step(p, rg, np.zeros_like(p), np.zeros_like(p), 1, 1e-3)
+    big = np.abs(rg) > 1e-4 * np.abs(rg).max()
+    assert np.all(np.abs(p1 - rp)[big] <= 1e-6 + 1e-6 * np.abs(rp[big]))
+    # no step is longer than lr, up to the float32 rounding of the update
+    assert np.all(np.abs(p1 - p) <= 1e-3 * (1 + 1e-5) + 2.0 ** -22 * np.abs(p))
+
+
+def test_training_fits_a_smooth_target_and_roundtrips_through_a_file():
+    X, y = _data(2000, 8)
+    H.hf_mlp_init(D, 9)
+    loss = H.hf_mlp_train(X, y, epochs=1500, lr=2e-3)
+    assert loss < 0.1  # standardised MSE: the target's variance is 1
+    Xt, yt = _data(500, 10)
+    pred = H.hf_mlp_predict(Xt)
+    assert np.corrcoef(pred, yt)[0, 1] > 0.8
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "m.bin")
+        H.hf_mlp_save(path)
+        H.hf_mlp_init(D, 123)
+        H.hf_mlp_load(path)
+    assert np.array_equal(H.hf_mlp_predict(Xt), pred)
+
+
+def test_learned_tuner_beats_the_untuned_choice():
+    """Trains on tuner-profiled samples of some pairs, then on held-out pairs
+    the model's top-3 choice is compared with the even split (the method
+    without the network) and with 3 random candidates."""
+    pairs = LT.draw_pairs(12, seed=5, kmin=18, kmax=23)
+    data = LT.collect(pairs, reps=5, seed=5)
+    res = LT.evaluate(data, folds=3, per_pair=50, topk=3, epochs=1500)
+    print({k: v for k, v in res.items() if k != "per_pair"}, flush=True)
+    assert res["regret_mlp_mean"] < res["regret_naive_mean"]
+    assert res["regret_mlp_mean"] <= 0.10
+
+
+def test_hf_tune_mlp_profiles_only_topk():
+    pairs = LT.draw_pairs(6, seed=6, kmin=18, kmax=22)
+    data = LT.collect(pairs, reps=3, seed=6)
+    H.hf_mlp_init(D, 0)
+    H.hf_mlp_train(data["X"], data["y"], epochs=800, lr=2e-3)
+    ia, ib = LT.Instance(0, 20, 1), LT.Instance(1, 20, 2)
+    pr = H.make_pair(ia.task, ib.task)
+    best, st = H.hf_tune(pr, H.HF_TUNE_MLP, 0, 3)
+    assert st["n_profiled"] == 3 and st["n_candidates"] == 85
+    assert H.hf_validate_fused(pr, best) == H.HF_OK
