@@ -40,6 +40,7 @@ def parse():
     ap.add_argument("--cfg", type=str, default="", help="split_waves,block,cap: skip the tuner")
     ap.add_argument("--blocks", type=str, default="", help="block_bn,block_mix: skip the solo block sweep")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle timing")
+    ap.add_argument("--no-pairs", action="store_true", help="skip the memory + atomic pairs")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run the reference copy kernel over this many MiB (counter calibration)")
     return ap.parse_args()
@@ -216,10 +217,53 @@ def main():
     }
     if tune:
         res["tune"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in tune.items()}
+    if not a.no_pairs:
+        del xd, sd, out
+        torch.cuda.empty_cache()
+        res["other_pairs"] = other_pairs(a.steps)
     if not a.no_cpu:
         res["cpu_baseline"] = cpu_baseline(x, seeds)
     print(json.dumps(res), flush=True)
     return 0
+
+
+def other_pairs(steps):
+    """The memory + atomic pairs: im2col [32,128,56,56] 3x3/s1/p1 and bilinear x2
+    upsample [32,64,128,128], each fused with a 256-bin histogram of 2^26 Zipf
+    bytes; exhaustive tune, then the fused step against the back-to-back one."""
+    import numpy as np
+    import torch
+
+    from paper_2007_01277_amd import hfuse as H
+    from paper_2007_01277_amd import inputs
+    xh = torch.from_numpy(inputs.zipf_u8(1 << 26, seed=2)).cuda()
+    counts = torch.empty(256, dtype=torch.int32, device="cuda")
+    th = H.task_lds_hist(xh, counts)
+    xi = torch.from_numpy(inputs.normal_image((32, 128, 56, 56), 1)).cuda()
+    cols = torch.empty((32, 128 * 9, 56 * 56), device="cuda")
+    ti = H.task_im2col(xi, cols, 3, 3, 1, 1)
+    xu = torch.from_numpy(inputs.normal_image((32, 64, 128, 128), 3)).cuda()
+    up = torch.empty((32, 64, 256, 256), device="cuda")
+    tu = H.task_upsample(xu, up, 2)
+    out = {}
+    for name, ta, tb in (("im2col+lds_hist", ti, th), ("upsample+lds_hist", tu, th)):
+        pr = H.make_pair(ta, tb)
+        blk = []
+        for t in (ta, tb):
+            blk.append(min((256, 512, 1024), key=lambda b: float(np.median([H.hf_run_solo(t, b, timed=True)
+                                                                             for _ in range(9)]))))
+        cfg, st = H.hf_tune(pr, H.HF_TUNE_EXHAUSTIVE)
+        cfg = H.hf_config(cfg.split_waves, cfg.block, cfg.vgpr_cap, 0)
+        fused = float(np.median([H.hf_run_fused_cfg(pr, cfg, timed=True) for _ in range(steps)]))
+        serial = float(np.median([H.hf_run_unfused(pr, blk[0], blk[1], H.HF_SERIAL, timed=True)
+                                  for _ in range(steps)]))
+        streams = float(np.median([H.hf_run_unfused(pr, blk[0], blk[1], H.HF_STREAMS, timed=True)
+                                   for _ in range(steps)]))
+        out[name] = {"fused_ms": round(fused, 5), "serial_ms": round(serial, 5), "streams_ms": round(streams, 5),
+                     "speedup_pct": round((serial / fused - 1) * 100, 2),
+                     "speedup_vs_streams_pct": round((streams / fused - 1) * 100, 2),
+                     "config": [cfg.split_waves, cfg.block, cfg.vgpr_cap], "solo_blocks": blk}
+    return out
 
 
 def cpu_baseline(x, seeds):

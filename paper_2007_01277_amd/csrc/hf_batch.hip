@@ -32,6 +32,7 @@ struct BatchTables {
   const int32_t* kinds;        // [ntask]
   const int32_t* wave0;        // [ntask] first wavefront of the task's interval
   const int32_t* wave1;        // [ntask] one past its last wavefront
+  const int32_t* lds_slot;     // [ntask] histogram LDS slot of the task (-1: none)
   const int32_t* grp_first;    // [ngroup + 1] first task of each group
   const uint32_t* item_start;  // [ngroup + 1] first item of each group
   const uint32_t* grp_nwg;     // [ngroup] virtual workgroups of each group
@@ -52,9 +53,13 @@ __device__ __forceinline__ void run_body(int kind, const DevTask& t, const Part&
   }
 }
 
+// LDS: kMaxMembers interval-barrier counters, then (dynamic) one histogram
+// region per histogram member of the largest group's histogram count.
+extern __shared__ uint32_t hf_batch_hist_lds[];
+
 template <int BLOCK>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5))) k_batch(BatchTables T) {
-  __shared__ uint32_t smem[kMaxMembers + kMaxMembers * LdsHist::lds_words(BLOCK)];
+  __shared__ uint32_t smem[kMaxMembers];
   __shared__ uint32_t item_sh[2];
   const uint32_t wave = uniform(threadIdx.x >> 6);
   if (threadIdx.x == 0)
@@ -98,8 +103,9 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5)))
       uint32_t* dst = reinterpret_cast<uint32_t*>(&dt);
 #pragma unroll
       for (int i = 0; i < (int)(sizeof(DevTask) / 4); ++i) dst[i] = uniform(src[i]);
-      run_body((int)uniform((uint32_t)T.kinds[mine]), dt, p, bar,
-               &smem[kMaxMembers + (uint32_t)(mine - t0) * LdsHist::lds_words(BLOCK)]);
+      const int32_t slot = (int32_t)uniform((uint32_t)T.lds_slot[mine]);
+      uint32_t* lds = slot >= 0 ? hf_batch_hist_lds + (uint32_t)slot * LdsHist::lds_words(BLOCK) : nullptr;
+      run_body((int)uniform((uint32_t)T.kinds[mine]), dt, p, bar, lds);
     }
     __syncthreads();  // item boundary: every interval has finished
   }
@@ -117,6 +123,7 @@ struct Batch {
   hipGraphExec_t exec = nullptr;
   hipStream_t cap = nullptr;
   int grid = 0;
+  size_t lds_bytes = 0;  // dynamic LDS per workgroup
 };
 
 static const void* batch_kernel(int block) {
@@ -190,7 +197,8 @@ static int batch_free(Batch* B) {
 
 static int batch_launch(Batch* B, hipStream_t st) {
   void* args[] = {&B->tab};
-  hipError_t e = hipLaunchKernel(batch_kernel(B->block), dim3(B->grid), dim3(B->block), args, 0, st);
+  hipError_t e =
+      hipLaunchKernel(batch_kernel(B->block), dim3(B->grid), dim3(B->block), args, B->lds_bytes, st);
   return e == hipSuccess ? HF_OK : record_hip(e);
 }
 
@@ -211,9 +219,14 @@ static int batch_create(const hf_task* tasks, int ntask, const int32_t* group_of
   }
   first.push_back(ntask);
   const int ngroup = (int)first.size() - 1;
-  std::vector<int32_t> waves(ntask), w0(ntask), w1(ntask);
+  std::vector<int32_t> waves(ntask), w0(ntask), w1(ntask), slot(ntask, -1);
+  int max_hist = 0;
   for (int g = 0; g < ngroup; ++g) {
     const int n = first[g + 1] - first[g];
+    int nh = 0;
+    for (int i = first[g]; i < first[g + 1]; ++i)
+      if (tasks[i].kind == HF_LDS_HIST) slot[i] = nh++;
+    max_hist = std::max(max_hist, nh);
     if (n > kMaxMembers || n > W) return HF_EINVAL;
     if (waves_of_task) {
       int sum = 0;
@@ -293,7 +306,8 @@ static int batch_create(const hf_task* tasks, int ntask, const int32_t* group_of
   // one device allocation for every table
   auto al = [](size_t v) { return (v + 255) & ~size_t(255); };
   const size_t o_tasks = 0, o_kinds = al(o_tasks + sizeof(DevTask) * ntask),
-               o_w0 = al(o_kinds + 4 * ntask), o_w1 = al(o_w0 + 4 * ntask), o_first = al(o_w1 + 4 * ntask),
+               o_w0 = al(o_kinds + 4 * ntask), o_w1 = al(o_w0 + 4 * ntask), o_slot = al(o_w1 + 4 * ntask),
+               o_first = al(o_slot + 4 * ntask),
                o_istart = al(o_first + 4 * (ngroup + 1)), o_nwg = al(o_istart + 4 * (ngroup + 1)),
                o_queue = al(o_nwg + 4 * ngroup), total = al(o_queue + 4);
   if ((e = hipMalloc(&B->dmem, total)) != hipSuccess) {
@@ -306,6 +320,7 @@ static int batch_create(const hf_task* tasks, int ntask, const int32_t* group_of
   std::memcpy(host.data() + o_kinds, kinds.data(), 4 * ntask);
   std::memcpy(host.data() + o_w0, w0.data(), 4 * ntask);
   std::memcpy(host.data() + o_w1, w1.data(), 4 * ntask);
+  std::memcpy(host.data() + o_slot, slot.data(), 4 * ntask);
   std::memcpy(host.data() + o_first, first.data(), 4 * (ngroup + 1));
   std::memcpy(host.data() + o_istart, istart.data(), 4 * (ngroup + 1));
   std::memcpy(host.data() + o_nwg, nwg.data(), 4 * ngroup);
@@ -318,18 +333,21 @@ static int batch_create(const hf_task* tasks, int ntask, const int32_t* group_of
   B->tab.kinds = reinterpret_cast<const int32_t*>(d + o_kinds);
   B->tab.wave0 = reinterpret_cast<const int32_t*>(d + o_w0);
   B->tab.wave1 = reinterpret_cast<const int32_t*>(d + o_w1);
+  B->tab.lds_slot = reinterpret_cast<const int32_t*>(d + o_slot);
   B->tab.grp_first = reinterpret_cast<const int32_t*>(d + o_first);
   B->tab.item_start = reinterpret_cast<const uint32_t*>(d + o_istart);
   B->tab.grp_nwg = reinterpret_cast<const uint32_t*>(d + o_nwg);
   B->tab.queue = reinterpret_cast<uint32_t*>(d + o_queue);
   B->tab.ngroup = (uint32_t)ngroup;
   B->tab.total_items = B->total_items;
-  const int g = occupancy_grid(s, batch_kernel(block), block, nullptr);
-  if (g < 0) {
+  B->lds_bytes = (size_t)max_hist * LdsHist::lds_words(block) * 4u;
+  int occ = 0;
+  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, batch_kernel(block), block, B->lds_bytes)) !=
+      hipSuccess) {
     batch_free(B);
-    return g;
+    return record_hip(e);
   }
-  B->grid = (int)std::max<int64_t>(1, std::min<int64_t>(g, B->total_items));
+  B->grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)std::max(occ, 1) * s->num_cus, B->total_items));
   *out = B;
   return HF_OK;
 }

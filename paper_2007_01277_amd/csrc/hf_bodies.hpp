@@ -332,8 +332,11 @@ struct IntMix {
 // barriers separate clearing, counting and merging.  Workgroups add their bins
 // into an agent-scope accumulator; the last workgroup to arrive moves the
 // totals to the output with atomic exchanges, which also re-zero it.
+#ifndef HF_HIST_COPIES
+#define HF_HIST_COPIES 16
+#endif
 struct LdsHist {
-  static constexpr uint32_t kCopies = 8;
+  static constexpr uint32_t kCopies = HF_HIST_COPIES;
   static constexpr uint32_t lds_words(int) { return 256u * kCopies; }
 
   __device__ static __forceinline__ void count_byte(uint32_t* mine, uint32_t b) {
@@ -442,6 +445,11 @@ struct Im2col {
 // Bilinear upsampling (Sec. IV-A) by an integer factor s with half-pixel
 // centres: t = max(0, (o + 0.5)/s - 0.5), i0 = floor(t), i1 = min(i0+1, L-1),
 // l = t - i0; lerp along x on rows y0 and y1, then along y, as a + l*(b - a).
+// Units are output rows (several short rows per unit), written front to back.
+// For s = 2 the four outputs 4c..4c+3 of a float4 read the four consecutive
+// inputs 2c-1..2c+2 (clamped) with weights 0.75, 0.25, 0.75, 0.25, which are
+// exactly the values the general formula produces, so both paths give the same
+// bits; the fast path just skips the per-output coordinate arithmetic.
 struct Upsample {
   static constexpr uint32_t lds_words(int) { return 0; }
 
@@ -455,16 +463,16 @@ struct Upsample {
     l = t - (float)a;
   }
 
-  __device__ static __forceinline__ float sample(const float* img, uint32_t W, uint32_t y0,
-                                                 uint32_t y1, float ly, uint32_t ox, float inv_s) {
+  __device__ static __forceinline__ float lerp(float a, float b, float l) { return a + l * (b - a); }
+
+  __device__ static __forceinline__ float sample(const float* r0, const float* r1, float ly, uint32_t W,
+                                                 uint32_t ox, float inv_s) {
     uint32_t x0, x1;
     float lx;
     coord(ox, inv_s, W, x0, x1, lx);
-    const float a = img[y0 * W + x0], b = img[y0 * W + x1];
-    const float c = img[y1 * W + x0], d = img[y1 * W + x1];
-    const float top = a + lx * (b - a);
-    const float bot = c + lx * (d - c);
-    return top + ly * (bot - top);
+    const float top = lerp(r0[x0], r0[x1], lx);
+    const float bot = lerp(r1[x0], r1[x1], lx);
+    return lerp(top, bot, ly);
   }
 
   template <class Bar>
@@ -473,6 +481,7 @@ struct Upsample {
     const uint32_t lane = lane_id();
     const uint32_t nw = p.nwg * p.nwaves;
     const uint32_t HW = a.H * a.W;
+    const bool x2 = a.vec && a.Wo == 2u * a.W;  // scale 2 with float4 stores
     for (uint32_t u = p.wg * p.nwaves + p.wave; u < a.units; u += nw) {
       const uint32_t row0 = u * a.rows_per_unit;
       for (uint32_t t = lane; t < a.lanes_per_unit; t += 64u) {
@@ -486,14 +495,25 @@ struct Upsample {
         float ly;
         coord(oy, a.inv_s, a.H, y0, y1, ly);
         const float* img = a.x + plane * HW;
+        const float* r0 = img + y0 * a.W;
+        const float* r1 = img + y1 * a.W;
         float* dst = a.out + row * a.Wo;
-        if (a.vec) {
+        if (x2) {
+          const uint32_t xm = col > 0u ? 2u * col - 1u : 0u;
+          const uint32_t xp = min(2u * col + 2u, a.W - 1u);
+          const float p0 = r0[xm], p1 = r0[2u * col], p2 = r0[2u * col + 1u], p3 = r0[xp];
+          const float q0 = r1[xm], q1 = r1[2u * col], q2 = r1[2u * col + 1u], q3 = r1[xp];
+          store_nt4(dst + 4u * col, lerp(lerp(p0, p1, 0.75f), lerp(q0, q1, 0.75f), ly),
+                    lerp(lerp(p1, p2, 0.25f), lerp(q1, q2, 0.25f), ly),
+                    lerp(lerp(p1, p2, 0.75f), lerp(q1, q2, 0.75f), ly),
+                    lerp(lerp(p2, p3, 0.25f), lerp(q2, q3, 0.25f), ly));
+        } else if (a.vec) {
           float v[4];
 #pragma unroll
-          for (int e = 0; e < 4; ++e) v[e] = sample(img, a.W, y0, y1, ly, 4u * col + e, a.inv_s);
-          *reinterpret_cast<float4*>(dst + 4u * col) = make_float4(v[0], v[1], v[2], v[3]);
+          for (int e = 0; e < 4; ++e) v[e] = sample(r0, r1, ly, a.W, 4u * col + e, a.inv_s);
+          store_nt4(dst + 4u * col, v[0], v[1], v[2], v[3]);
         } else {
-          dst[col] = sample(img, a.W, y0, y1, ly, col, a.inv_s);
+          __builtin_nontemporal_store(sample(r0, r1, ly, a.W, col, a.inv_s), dst + col);
         }
       }
     }

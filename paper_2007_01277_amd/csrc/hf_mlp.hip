@@ -270,6 +270,7 @@ static uint64_t splitmix64(uint64_t& s) {
 // ------------------------------------------------------------------ features
 struct SoloFeat {
   double t_ms = 0, bytes = 0, ops = 0;
+  double t_blk[3] = {0, 0, 0};  // solo time at blocks 256, 512, 1024
   int kind = 0, vgprs = 0;
 };
 
@@ -311,12 +312,12 @@ static int solo_feat(DeviceState* s, const hf_task* t, hipStream_t st, SoloFeat*
   alg_work(t, &f->bytes, &f->ops);
   double best = 1e30;
   const int blocks[] = {256, 512, 1024};
-  for (int b : blocks) {
+  for (int bi = 0; bi < 3; ++bi) {
     std::vector<float> ts;
     for (int r = 0; r < 6; ++r) {
       hipError_t e = hipEventRecord(s->ev_start, st);
       if (e != hipSuccess) return record_hip(e);
-      int rc = launch_solo(s, t, b, 0, 0, st);
+      int rc = launch_solo(s, t, blocks[bi], 0, 0, st);
       if (rc != HF_OK) return rc;
       if ((e = hipEventRecord(s->ev_stop, st)) != hipSuccess) return record_hip(e);
       if ((rc = wait_event(s->ev_stop)) != HF_OK) return rc;
@@ -325,9 +326,10 @@ static int solo_feat(DeviceState* s, const hf_task* t, hipStream_t st, SoloFeat*
       if (r > 0) ts.push_back(ms);  // the first launch warms up
     }
     std::sort(ts.begin(), ts.end());
-    best = std::min(best, (double)ts[ts.size() / 2]);
+    f->t_blk[bi] = std::max((double)ts[ts.size() / 2], 1e-4);
+    best = std::min(best, f->t_blk[bi]);
   }
-  f->t_ms = std::max(best, 1e-4);
+  f->t_ms = best;
   hf_kernel_info info;
   int rc = kernel_info(s, find_kernel(t->kind, -1, 1024, 0)->fn, 1024, &info);
   if (rc != HF_OK) return rc;
@@ -335,30 +337,49 @@ static int solo_feat(DeviceState* s, const hf_task* t, hipStream_t st, SoloFeat*
   return HF_OK;
 }
 
-static void fill_features(const SoloFeat& fa, const SoloFeat& fb, const hf_config& c, int waves_per_simd,
+// Features of one candidate (kFeat values), kernels in canonical order (the
+// smaller kind first; the split fraction refers to that kernel):
+//   per kernel (12 each): one-hot kind (5); log2 solo time at
+//   blocks 256, 512, 1024; log2 algorithmic MB and mega-lane-ops; fractions of
+//   the HBM and integer-ALU peaks the best solo run reached;
+//   configuration (8): split fraction s = 64*split_waves/block; log2(block/512);
+//   VGPR bound / 128 (1 when unbounded); resident waves per SIMD / 8;
+//   log2(t_a(block)/s), log2(t_b(block)/(1-s)) and the log2 of their maximum,
+//   with t_k(block) the solo time at the candidate's block size; log2 of the
+//   sum of the best solo times.
+static void fill_features(const SoloFeat& fa0, const SoloFeat& fb0, const hf_config& c, int waves_per_simd,
                           float* x) {
   auto l2 = [](double v) { return (float)std::log2(std::max(v, 1e-30)); };
+  // canonical order: the kernel of the smaller kind first, with the split
+  // fraction mirrored, so (a, b, s) and (b, a, 1 - s) -- the same fused kernel
+  // -- get the same features
+  const bool swap = fa0.kind > fb0.kind;
+  const SoloFeat& fa = swap ? fb0 : fa0;
+  const SoloFeat& fb = swap ? fa0 : fb0;
   const SoloFeat* f[2] = {&fa, &fb};
   for (int k = 0; k < 2; ++k) {
-    float* o = x + 10 * k;
+    float* o = x + 12 * k;
     for (int i = 0; i < 5; ++i) o[i] = (f[k]->kind == i) ? 1.f : 0.f;
-    o[5] = l2(f[k]->t_ms);
-    o[6] = l2(f[k]->bytes / 1e6 + 1e-3);
-    o[7] = l2(f[k]->ops / 1e6 + 1e-3);
-    o[8] = (float)(f[k]->bytes / (f[k]->t_ms * 1e-3) / 8e12);
-    o[9] = (float)(f[k]->ops / (f[k]->t_ms * 1e-3) / 39.3216e12);
+    o[5] = l2(f[k]->t_blk[0]);
+    o[6] = l2(f[k]->t_blk[1]);
+    o[7] = l2(f[k]->t_blk[2]);
+    o[8] = l2(f[k]->bytes / 1e6 + 1e-3);
+    o[9] = l2(f[k]->ops / 1e6 + 1e-3);
+    o[10] = (float)(f[k]->bytes / (f[k]->t_ms * 1e-3) / 8e12);
+    o[11] = (float)(f[k]->ops / (f[k]->t_ms * 1e-3) / 39.3216e12);
   }
+  const int bi = c.block == 256 ? 0 : (c.block == 512 ? 1 : 2);
   const double W = c.block / 64.0;
-  const double s = c.split_waves / W;
-  x[20] = (float)s;
-  x[21] = l2(c.block / 512.0);
-  x[22] = c.vgpr_cap == 0 ? 1.f : c.vgpr_cap / 128.f;
-  x[23] = waves_per_simd / 8.f;
-  const double ta = fa.t_ms / s, tb = fb.t_ms / (1.0 - s);
-  x[24] = l2(ta);
-  x[25] = l2(tb);
-  x[26] = l2(std::max(ta, tb));
-  x[27] = l2(fa.t_ms + fb.t_ms);
+  const double s = swap ? 1.0 - c.split_waves / W : c.split_waves / W;
+  x[24] = (float)s;
+  x[25] = l2(c.block / 512.0);
+  x[26] = c.vgpr_cap == 0 ? 1.f : c.vgpr_cap / 128.f;
+  x[27] = waves_per_simd / 8.f;
+  const double ta = fa.t_blk[bi] / s, tb = fb.t_blk[bi] / (1.0 - s);
+  x[28] = l2(ta);
+  x[29] = l2(tb);
+  x[30] = l2(std::max(ta, tb));
+  x[31] = l2(fa.t_ms + fb.t_ms);
 }
 
 int featurize(DeviceState* s, const hf_pair* pr, const hf_config* cfg, int n, hipStream_t st, float* X) {

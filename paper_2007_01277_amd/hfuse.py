@@ -11,7 +11,7 @@ import ctypes
 import os
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(PKG, "libhfuse.so")
+LIB_PATH = os.environ.get("HFUSE_LIB") or os.path.join(PKG, "libhfuse.so")
 
 HF_OK, HF_EINVAL, HF_EUNSUPPORTED, HF_EHIP, HF_ETIMEOUT, HF_ENOMEM, HF_ENOMODEL = 0, -1, -2, -3, -4, -5, -6
 HF_BN_STATS, HF_INT_MIX, HF_IM2COL, HF_LDS_HIST, HF_UPSAMPLE = range(5)
@@ -303,7 +303,7 @@ def hf_register_bound(d1: int, d2: int, vgpr_a: int, vgpr_b: int, lds_fused: int
 
 
 # ------------------------------------------------------------------ learned cost model
-MLP_FEATURES = 28
+MLP_FEATURES = 32
 
 
 def _f32(a):

@@ -104,22 +104,24 @@ def test_training_fits_a_smooth_target_and_roundtrips_through_a_file():
 
 
 def test_learned_tuner_beats_the_untuned_choice():
-    """Trains on tuner-profiled samples of some pairs, then on held-out pairs
-    the model's top-3 choice is compared with the even split (the method
-    without the network) and with 3 random candidates."""
-    pairs = LT.draw_pairs(12, seed=5, kmin=18, kmax=23)
+    """Trains on tuner-profiled samples of 75 pairs (14 configurations each) and
+    ranks every candidate of 25 held-out pairs: the model's top-3 choice has a
+    lower regret than the even split (the method without the network) and than
+    3 candidates profiled at random, at 3/85 of the exhaustive search's cost."""
+    pairs = LT.draw_pairs(100, seed=5, kmin=16, kmax=22)
     data = LT.collect(pairs, reps=5, seed=5)
-    res = LT.evaluate(data, folds=3, per_pair=50, topk=3, epochs=1500)
+    res = LT.evaluate(data, folds=4, per_pair=14, topk=3, epochs=500)
     print({k: v for k, v in res.items() if k != "per_pair"}, flush=True)
     assert res["regret_mlp_mean"] < res["regret_naive_mean"]
-    assert res["regret_mlp_mean"] <= 0.10
+    assert res["regret_mlp_mean"] < res["regret_random_mean_at_k"][3]
+    assert res["regret_mlp_mean"] <= 0.08
 
 
 def test_hf_tune_mlp_profiles_only_topk():
     pairs = LT.draw_pairs(6, seed=6, kmin=18, kmax=22)
     data = LT.collect(pairs, reps=3, seed=6)
     H.hf_mlp_init(D, 0)
-    H.hf_mlp_train(data["X"], data["y"], epochs=800, lr=2e-3)
+    H.hf_mlp_train(data["X"], data["y"] - data["X"][:, LT.SUM_SOLO], epochs=500, lr=1e-3)
     ia, ib = LT.Instance(0, 20, 1), LT.Instance(1, 20, 2)
     pr = H.make_pair(ia.task, ib.task)
     best, st = H.hf_tune(pr, H.HF_TUNE_MLP, 0, 3)
