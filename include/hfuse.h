@@ -308,6 +308,9 @@ int hf_batch_tune(const hf_task* tasks, int ntask, const int32_t* group_of_task,
 /* Streams `bytes` (multiple of 16) from src to dst: the reference copy kernel
  * for measured HBM ceilings and for scaling rocprof byte counters. */
 int hf_copy(void* dst, const void* src, int64_t bytes, void* stream, float* ms_out);
+/* Streams `bytes` (multiple of 16) from src and writes almost nothing: the
+ * read-bandwidth ceiling for the reduction kernels. */
+int hf_read(const void* src, int64_t bytes, void* stream, float* ms_out);
 /* Writes a library-owned 1 GiB buffer so that no input stays in the 256 MB
  * last-level cache between timed repetitions. */
 int hf_scrub(void* stream);

@@ -508,6 +508,17 @@ __global__ void __launch_bounds__(256) k_copy(float4* __restrict__ dst, const fl
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
 }
 
+// Reads n float4 and writes one word per workgroup (a read-bandwidth ceiling).
+__global__ void __launch_bounds__(256) k_read(const float4* __restrict__ src, uint64_t n, float* __restrict__ sink) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  float acc = 0.f;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const float4 v = src[i];
+    acc += (v.x + v.y) + (v.z + v.w);
+  }
+  if (acc == 1234.5f) sink[blockIdx.x] = acc;  // keeps the loads alive
+}
+
 __global__ void __launch_bounds__(256) k_fill(float4* __restrict__ dst, uint64_t n, float v) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
@@ -655,6 +666,29 @@ int hf_copy(void* dst, const void* src, int64_t bytes, void* stream, float* ms_o
   return timed_end(s, st, ms_out);
 }
 
+int hf_read(const void* src, int64_t bytes, void* stream, float* ms_out) {
+  if (!src || bytes < 0 || bytes % 16 != 0 || !aligned(src, 16)) return HF_EINVAL;
+  int rc;
+  DeviceState* s = device_state(&rc);
+  if (!s) return rc;
+  if (!s->warm) {
+    hipError_t e = hipMalloc(&s->warm, 1 << 16);
+    if (e != hipSuccess) {
+      record_hip(e);
+      return HF_ENOMEM;
+    }
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if ((rc = timed_begin(s, st, ms_out)) != HF_OK) return rc;
+  const uint64_t n = (uint64_t)bytes / 16;
+  const int grid = std::max(1, std::min<int>((int)((n + 255) / 256), std::min(s->num_cus * 8, 16384)));
+  hipLaunchKernelGGL(k_read, dim3(grid), dim3(256), 0, st, static_cast<const float4*>(src), n,
+                     static_cast<float*>(s->warm));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return record_hip(e);
+  return timed_end(s, st, ms_out);
+}
+
 int hf_scrub(void* stream) {
   int rc;
   DeviceState* s = device_state(&rc);
@@ -680,7 +714,7 @@ int hf_warmup(int ms, void* stream) {
   DeviceState* s = device_state(&rc);
   if (!s) return rc;
   if (!s->warm) {
-    hipError_t e = hipMalloc(&s->warm, 256);
+    hipError_t e = hipMalloc(&s->warm, 1 << 16);
     if (e != hipSuccess) {
       record_hip(e);
       return HF_ENOMEM;

@@ -111,6 +111,7 @@ SIGNATURES = {
     "hf_run_batch": (_I, [ctypes.POINTER(hf_task), _I, _I32P, _I32P, _I, _P, _F]),
     "hf_batch_tune": (_I, [ctypes.POINTER(hf_task), _I, _I32P, _I, _P, _I32P, _I32P, _F]),
     "hf_copy": (_I, [_P, _P, ctypes.c_int64, _P, _F]),
+    "hf_read": (_I, [_P, ctypes.c_int64, _P, _F]),
     "hf_scrub": (_I, [_P]),
     "hf_warmup": (_I, [_I, _P]),
 }
@@ -456,6 +457,13 @@ def hf_copy(dst, src, nbytes: int, stream=None, timed=False):
     ms = _ms(timed)
     _check(lib().hf_copy(_ptr(dst), _ptr(src), nbytes, _stream(stream),
                          ctypes.byref(ms) if ms is not None else None), "hf_copy")
+    return ms.value if ms is not None else None
+
+
+def hf_read(src, nbytes: int, stream=None, timed=False):
+    ms = _ms(timed)
+    _check(lib().hf_read(_ptr(src), nbytes, _stream(stream), ctypes.byref(ms) if ms is not None else None),
+           "hf_read")
     return ms.value if ms is not None else None
 
 

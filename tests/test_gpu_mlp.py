@@ -88,9 +88,11 @@ def test_adam_step_matches_reference():
 
 
 def test_training_fits_a_smooth_target_and_roundtrips_through_a_file():
-    X, y = _data(2000, 8)
+    # the target uses 3 of the 32 inputs; 4000 samples and 600 epochs generalise
+    # (the float64 reference reaches a held-out correlation of 0.88 with them)
+    X, y = _data(4000, 8)
     H.hf_mlp_init(D, 9)
-    loss = H.hf_mlp_train(X, y, epochs=1500, lr=2e-3)
+    loss = H.hf_mlp_train(X, y, epochs=600, lr=2e-3)
     assert loss < 0.1  # standardised MSE: the target's variance is 1
     Xt, yt = _data(500, 10)
     pred = H.hf_mlp_predict(Xt)
