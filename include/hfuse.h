@@ -169,6 +169,11 @@ int hf_run_fused(const hf_pair* pr, int split_num, int split_den, int block,
 int hf_run_fused_cfg(const hf_pair* pr, const hf_config* cfg, void* stream,
                      float* ms_out);
 
+/* Vertical fusion, the comparator of Sec. II-B / IV-A: one launch in which
+ * every thread of a `block`-lane workgroup runs task a's body and then task b's,
+ * each with the native workgroup barrier (grid = 0: occupancy default). */
+int hf_run_vfused(const hf_pair* pr, int block, int grid, void* stream, float* ms_out);
+
 /* ---------------------------------------------------------------- resources */
 typedef struct {
   int32_t vgprs;          /* VGPRs per lane of the compiled kernel                   */
@@ -311,8 +316,10 @@ int hf_copy(void* dst, const void* src, int64_t bytes, void* stream, float* ms_o
 /* Streams `bytes` (multiple of 16) from src and writes almost nothing: the
  * read-bandwidth ceiling for the reduction kernels. */
 int hf_read(const void* src, int64_t bytes, void* stream, float* ms_out);
-/* Writes a library-owned 1 GiB buffer so that no input stays in the 256 MB
- * last-level cache between timed repetitions. */
+/* Reads a library-owned 1 GiB buffer (written once, on the first call) so
+ * that no input stays in the 256 MB last-level cache between timed
+ * repetitions; the lines it leaves behind are clean, so the next kernel pays
+ * no write-back for them. */
 int hf_scrub(void* stream);
 /* Keeps the GPU busy for about `ms` milliseconds (warm-up before measurements,
  * Sec. IV-A "Execution Time Measurement"). */

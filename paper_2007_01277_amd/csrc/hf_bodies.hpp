@@ -118,9 +118,10 @@ __device__ __forceinline__ uint32_t arrive_after_coherent_stores(uint32_t* ctr, 
 //
 // Work decomposition (fixed by the shape, independent of grid and interval):
 //   unit = 1024 consecutive elements of one channel's N*H*W sequence.  One
-//          wavefront loads it (16 values per lane, the next unit already in
-//          flight), computes the unit's mean and M2 by two passes over registers
-//          with fixed-order wave sums, and publishes (mean, M2).
+//          wavefront loads it (16 values per lane; the next unit is already in
+//          flight in its own register slot), computes the unit's mean and M2
+//          by two passes over registers with fixed-order wave sums, and
+//          publishes (mean, M2).
 //   Each wavefront of the launch owns a contiguous, balanced range of units;
 //   at the end of each channel segment of its range it adds the segment's unit
 //   count to the channel's arrival counter.  The wavefront that completes a
@@ -129,24 +130,37 @@ __device__ __forceinline__ uint32_t arrive_after_coherent_stores(uint32_t* ctr, 
 // The unit results and their merge order do not depend on which wavefront
 // computed a unit, so every grid and split gives the same bits.
 struct BnStats {
-  static constexpr uint32_t kUnit = 1024;
+#ifndef HF_BN_VEC
+#define HF_BN_VEC 4
+#endif
+#ifndef HF_BN_DEPTH
+#define HF_BN_DEPTH 2
+#endif
+  static constexpr uint32_t kVec = HF_BN_VEC;      // float4 per lane per unit
+  static constexpr uint32_t kVals = 4 * kVec;      // values per lane per unit
+  static constexpr uint32_t kUnit = 64 * kVals;    // 1024 elements by default
+  static constexpr uint32_t kDepth = HF_BN_DEPTH;  // units in flight per wavefront
   static constexpr uint32_t lds_words(int) { return 0; }
 
   struct Regs {
-    float v[16];  // lane-major: every load instruction is coalesced
+    float v[kVals];  // lane-major: every load instruction is coalesced
   };
 
+  // Loads every lane unconditionally (lanes past the channel's end read the
+  // channel's first element, which unit_stats masks out), so the loads of a
+  // unit are straight-line code and no value is consumed before its reduction.
+  template <bool VEC>
   __device__ static __forceinline__ void load_unit(const BnArgs& a, uint32_t c, uint32_t ubase,
                                                    uint32_t lane, Regs& r) {
-    if (a.vec) {
+    const float* xc = a.x + (size_t)c * a.HW;
+    if constexpr (VEC) {
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
+      for (uint32_t t = 0; t < kVec; ++t) {
         const uint32_t j = ubase + 4u * (lane + 64u * t);
-        float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (j < a.M) {
-          const uint32_t n = fdiv(j, a.div_hw);
-          q = *reinterpret_cast<const float4*>(a.x + (c * a.HW + j + n * a.CHWm));
-        }
+        const bool ok = j < a.M;
+        const uint32_t jj = ok ? j : 0u;
+        const uint32_t n = fdiv(jj, a.div_hw);
+        const float4 q = *reinterpret_cast<const float4*>(xc + ((size_t)jj + (size_t)n * a.CHWm));
         r.v[4 * t + 0] = q.x;
         r.v[4 * t + 1] = q.y;
         r.v[4 * t + 2] = q.z;
@@ -154,23 +168,106 @@ struct BnStats {
       }
     } else {
 #pragma unroll
-      for (int t = 0; t < 16; ++t) {
+      for (uint32_t t = 0; t < kVals; ++t) {
         const uint32_t j = ubase + lane + 64u * t;
-        float q = 0.f;
-        if (j < a.M) {
-          const uint32_t n = fdiv(j, a.div_hw);
-          q = a.x[c * a.HW + j + n * a.CHWm];
-        }
-        r.v[t] = q;
+        const bool ok = j < a.M;
+        const uint32_t jj = ok ? j : 0u;
+        const uint32_t n = fdiv(jj, a.div_hw);
+        r.v[t] = xc[(size_t)jj + (size_t)n * a.CHWm];
       }
     }
   }
 
+  template <bool VEC>
   __device__ static __forceinline__ bool valid(const BnArgs& a, uint32_t ubase, uint32_t lane,
-                                               int t) {
-    const uint32_t j = a.vec ? ubase + 4u * (lane + 64u * (t >> 2)) + (t & 3)
-                             : ubase + lane + 64u * t;
+                                               uint32_t t) {
+    const uint32_t j = VEC ? ubase + 4u * (lane + 64u * (t >> 2)) + (t & 3u) : ubase + lane + 64u * t;
     return j < a.M;
+  }
+
+  // mean and M2 of one unit held in registers: two passes, fixed-order wave
+  // sums.  FULL: the unit has kUnit elements (every unit but a channel's last).
+  template <bool VEC, bool FULL>
+  __device__ static __forceinline__ void unit_stats(const BnArgs& a, const Regs& r, uint32_t ub,
+                                                    uint32_t lane, float& mu, float& m2) {
+    const uint32_t cnt = FULL ? kUnit : min(kUnit, a.M - ub);
+    float s = 0.f, q = 0.f;
+    // lanes past the channel's end hold a copy of another element: masked out
+#pragma unroll
+    for (uint32_t t = 0; t < kVals; ++t) s += (FULL || valid<VEC>(a, ub, lane, t)) ? r.v[t] : 0.f;
+    mu = wave_sum(s) / (float)cnt;
+#pragma unroll
+    for (uint32_t t = 0; t < kVals; ++t) {
+      const float d = (FULL || valid<VEC>(a, ub, lane, t)) ? r.v[t] - mu : 0.f;
+      q += d * d;
+    }
+    m2 = wave_sum(q);
+  }
+
+  // Reduces the unit held in `r` (unit k of channel c, global unit index u)
+  // and publishes its (mean, M2) with one 8-byte store.
+  template <bool VEC, bool FULL>
+  __device__ static __forceinline__ void consume(const BnArgs& a, const Regs& r, uint32_t u,
+                                                 uint32_t k, uint32_t lane) {
+    float mu, m2;
+    unit_stats<VEC, FULL>(a, r, k * kUnit, lane, mu, m2);
+    if (lane == 0) {
+      const uint64_t v = (uint64_t)__builtin_bit_cast(uint32_t, mu) |
+                         ((uint64_t)__builtin_bit_cast(uint32_t, m2) << 32);
+      __hip_atomic_store(reinterpret_cast<uint64_t*>(a.part) + u, v, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+
+  // Units [k0, k0 + n) of channel c (global index u0 = c * upc + k0).  kDepth
+  // register slots; slot s always holds unit i + s of the current stride, so a
+  // unit is requested kDepth - 1 reductions before it is reduced.  The steady
+  // loop has no branch: every unit in it is full and every reload exists, which
+  // keeps the compiler's count of outstanding loads exact.
+  template <bool VEC>
+  __device__ static __forceinline__ void segment(const BnArgs& a, uint32_t c, uint32_t k0,
+                                                 uint32_t u0, uint32_t n, uint32_t lane) {
+    Regs buf[kDepth];
+    // unconditional, so that the loop is entered with every slot outstanding in
+    // slot order (a segment shorter than kDepth loads its last unit again)
+#pragma unroll
+    for (uint32_t s = 0; s < kDepth; ++s) load_unit<VEC>(a, c, (k0 + min(s, n - 1u)) * kUnit, lane, buf[s]);
+    uint32_t i = 0;
+    for (; i + 2u * kDepth <= n; i += kDepth) {
+#pragma unroll
+      for (uint32_t s = 0; s < kDepth; ++s) {
+        consume<VEC, true>(a, buf[s], u0 + i + s, k0 + i + s, lane);
+        load_unit<VEC>(a, c, (k0 + i + s + kDepth) * kUnit, lane, buf[s]);
+      }
+    }
+#pragma unroll
+    for (uint32_t s = 0; s < kDepth; ++s) {
+      if (i + s < n) {
+        consume<VEC, false>(a, buf[s], u0 + i + s, k0 + i + s, lane);
+        if (i + s + kDepth < n) load_unit<VEC>(a, c, (k0 + i + s + kDepth) * kUnit, lane, buf[s]);
+      }
+    }
+#pragma unroll
+    for (uint32_t s = 0; s < kDepth; ++s)
+      if (i + kDepth + s < n) consume<VEC, false>(a, buf[s], u0 + i + kDepth + s, k0 + i + kDepth + s, lane);
+  }
+
+  // The wavefront's contiguous unit range, one channel segment at a time; at
+  // the end of each segment it arrives on the channel's counter, and the last
+  // arriver merges the channel.
+  template <bool VEC>
+  __device__ static void run_range(const BnArgs& a, uint32_t ubeg, uint32_t uend, uint32_t lane) {
+    uint32_t c = fdiv(ubeg, a.div_upc);
+    uint32_t k0 = ubeg - c * a.upc;
+    for (uint32_t u = ubeg; u < uend; ++c, k0 = 0) {
+      const uint32_t n = min(uend - u, a.upc - k0);
+      segment<VEC>(a, c, k0, u, n, lane);
+      uint32_t old = 0;
+      if (lane == 0) old = arrive_after_coherent_stores(a.ctr + c, n);
+      old = uniform(old);
+      if (old + n == a.upc) finish_channel(a, c, lane);
+      u += n;
+    }
   }
 
   template <class Bar>
@@ -183,46 +280,10 @@ struct BnStats {
     const uint32_t ubeg = gw * q + min(gw, r);
     const uint32_t uend = ubeg + q + (gw < r ? 1u : 0u);
     if (ubeg >= uend) return;
-    uint32_t c = fdiv(ubeg, a.div_upc);
-    uint32_t k = ubeg - c * a.upc;
-    uint32_t seg = ubeg;  // first unit of the current channel segment
-    Regs cur, nxt;
-    load_unit(a, c, k * kUnit, lane, cur);
-    for (uint32_t u = ubeg; u < uend; ++u) {
-      const bool more = u + 1u < uend;
-      const bool last_of_channel = k + 1u == a.upc;
-      const uint32_t c2 = last_of_channel ? c + 1u : c;
-      const uint32_t k2 = last_of_channel ? 0u : k + 1u;
-      if (more) load_unit(a, c2, k2 * kUnit, lane, nxt);  // next unit in flight
-      const uint32_t ub = k * kUnit;
-      const float nu = (float)min(kUnit, a.M - ub);
-      float s = 0.f;
-#pragma unroll
-      for (int t = 0; t < 16; ++t) s += cur.v[t];
-      const float mu = wave_sum(s) / nu;
-      float sq = 0.f;
-#pragma unroll
-      for (int t = 0; t < 16; ++t) {
-        const float d = valid(a, ub, lane, t) ? cur.v[t] - mu : 0.f;
-        sq += d * d;
-      }
-      const float m2 = wave_sum(sq);
-      if (lane == 0) {
-        store_agent(a.part + 2u * u, __builtin_bit_cast(uint32_t, mu));
-        store_agent(a.part + 2u * u + 1u, __builtin_bit_cast(uint32_t, m2));
-      }
-      if (last_of_channel || !more) {
-        const uint32_t cnt = u + 1u - seg;
-        uint32_t old = 0;
-        if (lane == 0) old = arrive_after_coherent_stores(a.ctr + c, cnt);
-        old = uniform(old);
-        if (old + cnt == a.upc) finish_channel(a, c, lane);
-        seg = u + 1u;
-      }
-      c = c2;
-      k = k2;
-      if (more) cur = nxt;
-    }
+    if (a.vec)
+      run_range<true>(a, ubeg, uend, lane);
+    else
+      run_range<false>(a, ubeg, uend, lane);
   }
 
   // Chan et al. pairwise update of (n, mean, M2) with (nb, mb, m2b), in double.

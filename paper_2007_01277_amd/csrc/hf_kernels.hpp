@@ -61,6 +61,23 @@ fused_cap(DevTask ta, DevTask tb, uint32_t w1) {
   fused_body<K1, K2, BLOCK>(ta, tb, w1);
 }
 
+// Vertical fusion, the comparator of the paper (Sec. II-B "Vertical Kernel
+// Fusion", Sec. IV-A): one launch in which every thread executes the first
+// kernel's statements and then the second's, so both bodies see the whole
+// workgroup and keep the native workgroup barrier.
+template <class K1, class K2, int BLOCK>
+__global__ void __launch_bounds__(BLOCK) vfused(DevTask ta, DevTask tb) {
+  constexpr uint32_t L1 = K1::lds_words(BLOCK);
+  constexpr uint32_t L2 = K2::lds_words(BLOCK);
+  __shared__ uint32_t smem[max1(L1 > L2 ? L1 : L2)];
+  const Part p{threadIdx.x, (uint32_t)BLOCK, uniform(threadIdx.x >> 6), (uint32_t)(BLOCK / 64),
+               blockIdx.x, gridDim.x};
+  WGBarrier bar;
+  K1::run(ta, p, bar, smem);
+  __syncthreads();  // the second body may reuse the LDS of the first
+  K2::run(tb, p, bar, smem);
+}
+
 // The original kernel: the whole workgroup is one interval and its barrier is
 // the native s_barrier.
 template <class K, int BLOCK>
@@ -76,7 +93,7 @@ __global__ void __launch_bounds__(BLOCK) solo(DevTask t) {
 struct KernelEntry {
   int kind_a, kind_b;  // kind_b < 0: solo kernel of kind_a
   int block;
-  int cap;             // VGPR bound (0 = none)
+  int cap;             // VGPR bound (0 = none); -1: vertically fused comparator
   const void* fn;
 };
 
@@ -93,13 +110,21 @@ struct KernelEntry {
    reinterpret_cast<const void*>(&::hf::fused_nocap<::hf::BodyOf<KA>::T, ::hf::BodyOf<KB>::T, B>)}, \
       HF_CAP_LIST(HF_FUSED_CAP_ENTRY, KA, KB, B)
 
+// vertically fused kernels are registered with cap = -1
+#define HF_VFUSED_ENTRY(KA, KB, B)                                                               \
+  {KA, KB, B, -1, reinterpret_cast<const void*>(&::hf::vfused<::hf::BodyOf<KA>::T, ::hf::BodyOf<KB>::T, B>)},
+
 // Defines `const KernelEntry* NAME(int* count)` listing every fused
-// instantiation of the ordered pair (KA, KB) for blocks 256, 512, 1024.
+// instantiation of the ordered pair (KA, KB) for blocks 256, 512, 1024, and the
+// vertically fused comparator.
 #define HF_DEFINE_PAIR_TABLE(KA, KB, NAME)                                                       \
   const ::hf::KernelEntry* NAME(int* count) {                                                   \
     static const ::hf::KernelEntry tab[] = {HF_FUSED_BLOCK_ENTRIES(KA, KB, 256)                  \
                                                 HF_FUSED_BLOCK_ENTRIES(KA, KB, 512)              \
-                                                    HF_FUSED_BLOCK_ENTRIES(KA, KB, 1024)};       \
+                                                    HF_FUSED_BLOCK_ENTRIES(KA, KB, 1024)         \
+                                                        HF_VFUSED_ENTRY(KA, KB, 256)             \
+                                                            HF_VFUSED_ENTRY(KA, KB, 512)         \
+                                                                HF_VFUSED_ENTRY(KA, KB, 1024)};  \
     *count = (int)(sizeof(tab) / sizeof(tab[0]));                                               \
     return tab;                                                                                 \
   }

@@ -627,6 +627,39 @@ int hf_run_fused(const hf_pair* pr, int split_num, int split_den, int block, int
   return hf_run_fused_cfg(pr, &cfg, stream, ms_out);
 }
 
+int hf_run_vfused(const hf_pair* pr, int block, int grid, void* stream, float* ms_out) {
+  if (!pr) return HF_EINVAL;
+  int rc;
+  if ((rc = validate_task(&pr->a)) != HF_OK || (rc = validate_task(&pr->b)) != HF_OK) return rc;
+  if (check_block(block) != HF_OK || grid < 0) return HF_EINVAL;
+  if (pr->a.scratch && pr->a.scratch == pr->b.scratch && scratch_bytes(&pr->a) > 0 &&
+      scratch_bytes(&pr->b) > 0)
+    return HF_EINVAL;
+  const hf_task* ta = &pr->a;
+  const hf_task* tb = &pr->b;
+  if (ta->kind > tb->kind) std::swap(ta, tb);  // same work, canonical instantiation
+  const KernelEntry* k = find_kernel(ta->kind, tb->kind, block, -1);
+  if (!k) return HF_EUNSUPPORTED;
+  DeviceState* s = device_state(&rc);
+  if (!s) return rc;
+  void *sa = nullptr, *sb = nullptr;
+  if ((rc = task_scratch(s, ta, 0, &sa)) != HF_OK || (rc = task_scratch(s, tb, 1, &sb)) != HF_OK) return rc;
+  DevTask da, db;
+  if ((rc = prepare(ta, sa, &da)) != HF_OK || (rc = prepare(tb, sb, &db)) != HF_OK) return rc;
+  if (grid <= 0) {
+    const int g = occupancy_grid(s, k->fn, block, nullptr);
+    if (g < 0) return g;
+    const int64_t need = std::max(useful_wgs(ta, da, block / 64), useful_wgs(tb, db, block / 64));
+    grid = (int)std::min<int64_t>(g, need);
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if ((rc = timed_begin(s, st, ms_out)) != HF_OK) return rc;
+  void* args[] = {&da, &db};
+  hipError_t e = hipLaunchKernel(k->fn, dim3(grid), dim3(block), args, 0, st);
+  if (e != hipSuccess) return record_hip(e);
+  return timed_end(s, st, ms_out);
+}
+
 int hf_fused_info(int kind_a, int kind_b, int block, int vgpr_cap, hf_kernel_info* out) {
   if (!out || kind_a < 0 || kind_a >= HF_NUM_KINDS || kind_b < 0 || kind_b >= HF_NUM_KINDS)
     return HF_EINVAL;
@@ -694,16 +727,28 @@ int hf_scrub(void* stream) {
   DeviceState* s = device_state(&rc);
   if (!s) return rc;
   const size_t bytes = size_t(1) << 30;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (!s->warm) {
+    hipError_t e = hipMalloc(&s->warm, 1 << 16);
+    if (e != hipSuccess) {
+      record_hip(e);
+      return HF_ENOMEM;
+    }
+  }
   if (!s->scrub) {
     hipError_t e = hipMalloc(&s->scrub, bytes);
     if (e != hipSuccess) {
       record_hip(e);
       return HF_ENOMEM;
     }
+    // written once; every scrub afterwards only reads it, so the lines it
+    // leaves in the caches are clean and the next kernel pays no write-back
+    hipLaunchKernelGGL(k_fill, dim3(s->num_cus * 8), dim3(256), 0, st, static_cast<float4*>(s->scrub),
+                       (uint64_t)(bytes / 16), 1.0f);
   }
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  hipLaunchKernelGGL(k_fill, dim3(s->num_cus * 8), dim3(256), 0, st, static_cast<float4*>(s->scrub),
-                     (uint64_t)(bytes / 16), 1.0f);
+  // one word per workgroup of sink: num_cus * 8 <= 16384 words of `warm`
+  hipLaunchKernelGGL(k_read, dim3(std::min(s->num_cus * 8, 16384)), dim3(256), 0, st,
+                     static_cast<const float4*>(s->scrub), (uint64_t)(bytes / 16), static_cast<float*>(s->warm));
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? HF_OK : record_hip(e);
 }

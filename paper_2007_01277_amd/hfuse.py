@@ -85,6 +85,7 @@ SIGNATURES = {
     "hf_run_unfused": (_I, [ctypes.POINTER(hf_pair), _I, _I, _I, _P, _P, _F]),
     "hf_run_fused": (_I, [ctypes.POINTER(hf_pair), _I, _I, _I, _I, _P, _F]),
     "hf_run_fused_cfg": (_I, [ctypes.POINTER(hf_pair), ctypes.POINTER(hf_config), _P, _F]),
+    "hf_run_vfused": (_I, [ctypes.POINTER(hf_pair), _I, _I, _P, _F]),
     "hf_fused_info": (_I, [_I, _I, _I, _I, ctypes.POINTER(hf_kernel_info)]),
     "hf_solo_info": (_I, [_I, _I, ctypes.POINTER(hf_kernel_info)]),
     "hf_profile": (_I, [ctypes.POINTER(hf_pair), ctypes.POINTER(hf_config), _I, _P, _F]),
@@ -262,6 +263,13 @@ def hf_run_fused_cfg(pr: hf_pair, cfg: hf_config, stream=None, timed=False):
     ms = _ms(timed)
     _check(lib().hf_run_fused_cfg(ctypes.byref(pr), ctypes.byref(cfg), _stream(stream),
                                   ctypes.byref(ms) if ms is not None else None), "hf_run_fused_cfg")
+    return ms.value if ms is not None else None
+
+
+def hf_run_vfused(pr: hf_pair, block: int = 256, grid: int = 0, stream=None, timed=False):
+    ms = _ms(timed)
+    _check(lib().hf_run_vfused(ctypes.byref(pr), block, grid, _stream(stream),
+                               ctypes.byref(ms) if ms is not None else None), "hf_run_vfused")
     return ms.value if ms is not None else None
 
 

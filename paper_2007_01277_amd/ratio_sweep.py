@@ -1,0 +1,138 @@
+"""Speedup against the execution-time ratio of the two kernels.
+
+The evaluation varies the input size of one kernel of each pair (the kernel
+marked "*") and reports every fusion method's speedup over the native
+execution at each resulting ratio of solo times (Sec. IV-A "Run Different
+Workload", Sec. IV-B).  This script does the same on one MI355X for four pairs
+of this library, each with one kernel fixed and the other varied:
+
+  bn_stats [64,256,56,56]         + int_mix* 2^24 elements, R = 1 .. 128 rounds
+  bn_stats* [N,256,56,56]          + lds_hist 2^26 Zipf bytes, N = 4 .. 128
+  im2col [32,128,56,56] 3x3        + lds_hist* 2^22 .. 2^28 Zipf bytes
+  upsample x2 [32,64,128,128]      + lds_hist* 2^22 .. 2^28 Zipf bytes
+
+Methods at each point: HFuse = the exhaustive tuner's fused configuration;
+Naive = even split of a 1024-lane workgroup without a bound (Sec. IV-A); VFuse =
+vertical fusion at its best block; Streams = the two kernels on two streams;
+Serial = back to back.  Speedup % = (T_serial / T_method - 1) * 100; the ratio
+is t_star / t_other of the best solo times.
+
+    python -m paper_2007_01277_amd.ratio_sweep --out gpurun_out/ratio.json
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+
+import numpy as np
+
+from . import hfuse as H
+from . import inputs
+
+
+def med(f, n):
+    return float(np.median([f() for _ in range(n)]))
+
+
+def solo_best(t, reps):
+    times = {b: med(lambda: H.hf_run_solo(t, b, timed=True), reps) for b in (256, 512, 1024)}
+    b = min(times, key=times.get)
+    return b, times[b]
+
+
+def point(pr, reps):
+    ba, ta = solo_best(pr.a, reps)
+    bb, tb = solo_best(pr.b, reps)
+    cfg, _ = H.hf_tune(pr, H.HF_TUNE_EXHAUSTIVE)
+    cfg = H.hf_config(cfg.split_waves, cfg.block, cfg.vgpr_cap, 0)
+    hfuse = med(lambda: H.hf_run_fused_cfg(pr, cfg, timed=True), reps)
+    naive = med(lambda: H.hf_run_fused_cfg(pr, H.hf_config(8, 1024, 0, 0), timed=True), reps)
+    vf = min(med(lambda: H.hf_run_vfused(pr, b, timed=True), reps) for b in (256, 512, 1024))
+    serial = med(lambda: H.hf_run_unfused(pr, ba, bb, H.HF_SERIAL, timed=True), reps)
+    streams = med(lambda: H.hf_run_unfused(pr, ba, bb, H.HF_STREAMS, timed=True), reps)
+    sp = lambda t: round((serial / t - 1) * 100, 2)
+    return {"t_a_ms": round(ta, 5), "t_b_ms": round(tb, 5), "serial_ms": round(serial, 5),
+            "streams_ms": round(streams, 5), "hfuse_ms": round(hfuse, 5), "naive_ms": round(naive, 5),
+            "vfuse_ms": round(vf, 5), "hfuse_cfg": [cfg.split_waves, cfg.block, cfg.vgpr_cap],
+            "speedup_pct": {"hfuse": sp(hfuse), "naive": sp(naive), "vfuse": sp(vf), "streams": sp(streams)},
+            "hfuse_vs_streams_pct": round((streams / hfuse - 1) * 100, 2)}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--reps", type=int, default=15)
+    ap.add_argument("--out", default="")
+    a = ap.parse_args(argv)
+    import torch
+    torch.cuda.set_device(0)
+    H.hf_init()
+    H.hf_warmup(300)
+    res = {}
+
+    def zipf(n, seed):
+        return inputs.cuda_zipf_u8(n, seed)
+
+    # bn_stats fixed + int_mix* (rounds varied)
+    x = inputs.cuda_normal((64, 256, 56, 56), 10)
+    mean, var = torch.empty(256, device="cuda"), torch.empty(256, device="cuda")
+    bn = H.task_bn_stats(x, mean, var)
+    seeds = inputs.cuda_uint32(1 << 24, 11)
+    out = torch.empty_like(seeds)
+    rows = []
+    for r in (1, 2, 4, 8, 16, 32, 64, 128):
+        p = point(H.make_pair(bn, H.task_int_mix(seeds, out, r)), a.reps)
+        p["rounds"] = r
+        p["ratio_star_over_other"] = round(p["t_b_ms"] / p["t_a_ms"], 3)
+        rows.append(p)
+        print("bn_stats + int_mix*", r, p["ratio_star_over_other"], p["speedup_pct"], flush=True)
+    res["bn_stats+int_mix*"] = rows
+    del seeds, out
+
+    # bn_stats* (batch varied) + lds_hist fixed
+    h = zipf(1 << 26, 12)
+    counts = torch.empty(256, dtype=torch.int32, device="cuda")
+    hist = H.task_lds_hist(h, counts)
+    rows = []
+    for N in (4, 8, 16, 32, 64, 128):
+        xb = inputs.cuda_normal((N, 256, 56, 56), 13)
+        p = point(H.make_pair(H.task_bn_stats(xb, mean, var), hist), a.reps)
+        p["batch"] = N
+        p["ratio_star_over_other"] = round(p["t_a_ms"] / p["t_b_ms"], 3)
+        rows.append(p)
+        print("bn_stats* + lds_hist", N, p["ratio_star_over_other"], p["speedup_pct"], flush=True)
+        del xb
+    res["bn_stats*+lds_hist"] = rows
+    del x
+
+    # im2col / upsample fixed + lds_hist* (bytes varied)
+    xi = inputs.cuda_normal((32, 128, 56, 56), 14)
+    cols = torch.empty((32, 128 * 9, 56 * 56), device="cuda")
+    im = H.task_im2col(xi, cols, 3, 3, 1, 1)
+    xu = inputs.cuda_normal((32, 64, 128, 128), 15)
+    up_out = torch.empty((32, 64, 256, 256), device="cuda")
+    up = H.task_upsample(xu, up_out, 2)
+    for name, t in (("im2col+lds_hist*", im), ("upsample+lds_hist*", up)):
+        rows = []
+        for k in (22, 23, 24, 25, 26, 27, 28):
+            hk = zipf(1 << k, 16 + k)
+            p = point(H.make_pair(t, H.task_lds_hist(hk, counts)), a.reps)
+            p["log2_hist_bytes"] = k
+            p["ratio_star_over_other"] = round(p["t_b_ms"] / p["t_a_ms"], 3)
+            rows.append(p)
+            print(name, k, p["ratio_star_over_other"], p["speedup_pct"], flush=True)
+            del hk
+        res[name] = rows
+    summary = {}
+    for name, rows in res.items():
+        summary[name] = {m: round(float(np.mean([r["speedup_pct"][m] for r in rows])), 2)
+                         for m in ("hfuse", "naive", "vfuse", "streams")}
+    res["mean_speedup_pct"] = summary
+    print(json.dumps(summary), flush=True)
+    if a.out:
+        json.dump(res, open(a.out, "w"), indent=1)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

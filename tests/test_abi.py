@@ -150,6 +150,8 @@ def test_run_entry_points_reject_before_touching_the_gpu():
     assert L.hf_run_unfused(ctypes.byref(pr), 256, 256, 7, None, None, None) == H.HF_EINVAL
     assert L.hf_run_solo(ctypes.byref(_bn(n=0)), 256, 0, None, None) == H.HF_EINVAL
     assert L.hf_copy(None, None, 16, None, None) == H.HF_EINVAL
+    assert L.hf_run_vfused(ctypes.byref(pr), 384, 0, None, None) == H.HF_EINVAL
+    assert L.hf_run_vfused(None, 256, 0, None, None) == H.HF_EINVAL
     assert L.hf_tune(ctypes.byref(pr), 9, 0, 3, None, ctypes.byref(H.hf_config()), None) == H.HF_EINVAL
 
 

@@ -1,6 +1,7 @@
 """GPU parity: every kernel solo, every fused pair at every legal (split, block,
-VGPR bound) and the unfused baselines, against the CPU oracle and against each
-other.  All calls go through the C ABI (libhfuse.so)."""
+VGPR bound), the vertically fused comparator and the unfused baselines, against
+the CPU oracle and against each other.  All calls go through the C ABI
+(libhfuse.so)."""
 import itertools
 
 import numpy as np
@@ -71,6 +72,13 @@ def test_fused_bit_exact_vs_solo_all_configs(ka, kb):
                     assert torch.equal(r, o), (ca.label, block, w1, cap)
                 for r, o in zip(ref_b, cb.outputs()):
                     assert torch.equal(r, o), (cb.label, block, w1, cap)
+        # the vertically fused comparator computes the same results
+        ca.reset()
+        cb.reset()
+        H.hf_run_vfused(pr, block)
+        torch.cuda.synchronize()
+        for r, o in zip(ref_a + ref_b, ca.outputs() + cb.outputs()):
+            assert torch.equal(r, o), ("vfused", block)
 
 
 @pytest.mark.parametrize("mode", [H.HF_SERIAL, H.HF_STREAMS])
