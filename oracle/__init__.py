@@ -55,6 +55,8 @@ def _load():
         lib.oracle_upsample.restype = ctypes.c_int
         lib.oracle_upsample_absmag.argtypes = [P, I64, I64, I64, I64, I32, P]
         lib.oracle_upsample_absmag.restype = ctypes.c_int
+        lib.oracle_maxpool.argtypes = [P, I64, I64, I64, I64, I32, I32, I32, I32, P, P]
+        lib.oracle_maxpool.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -126,3 +128,22 @@ def upsample_absmag(x: np.ndarray, scale: int) -> np.ndarray:
     if rc != 0:
         raise ValueError("bad upsample parameters")
     return out
+
+
+def maxpool_shape(N, C, H, W, kh, kw, s, p):
+    return (N, C, (H + 2 * p - kh) // s + 1, (W + 2 * p - kw) // s + 1)
+
+
+def maxpool(x: np.ndarray, kh: int, kw: int, stride: int, pad: int):
+    """(max, flat argmax index h*W + w as int32) of every pooling window."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    N, C, H, W = x.shape
+    shape = maxpool_shape(N, C, H, W, kh, kw, stride, pad)
+    if shape[2] <= 0 or shape[3] <= 0:
+        raise ValueError("empty maxpool output")
+    out = np.empty(shape, np.float32)
+    idx = np.empty(shape, np.int32)
+    rc = _load().oracle_maxpool(_ptr(x), N, C, H, W, kh, kw, stride, pad, _ptr(out), _ptr(idx))
+    if rc != 0:
+        raise ValueError("bad maxpool parameters")
+    return out, idx

@@ -22,6 +22,14 @@
  *     centres (align_corners = false), source coordinate clamped at 0, upper
  *     neighbour clamped at the last row/column, linear interpolation written as
  *     a + l*(b - a), first along x then along y.
+ *   - maxpool  : "Maxpool applies a 2D maxpooling over an input matrix" (Sec.
+ *     IV-A; the kernel is PyTorch's).  Readings taken: square-or-rectangular
+ *     window kh x kw, one stride, one zero-count padding (padded positions never
+ *     win), floor output size, no dilation; outputs the maximum and the flat
+ *     index h*W + w of the element it came from.  The scan order is row-major
+ *     over the window; an element replaces the running maximum when it is
+ *     greater or is NaN, and the first valid element starts the scan, so ties
+ *     keep the first occurrence and a NaN propagates (the last NaN's index).
  *   - int_mix  : stands in for the compute-bound hash kernels of Sec. IV-A.  It
  *     is not defined by the paper; the definition fixed here is R rounds of
  *       x ^= x << 13;  x ^= x >> 17;  x ^= x << 5;    (Marsaglia's xorshift32)
@@ -186,6 +194,48 @@ OR_EXPORT int oracle_upsample_absmag(const float* x, int64_t N, int64_t C,
                               fabs(ly * lx * img[y1 * W + x1]);
         }
       }
+    }
+  return 0;
+}
+
+/* ------------------------------------------------------------------- maxpool */
+/* out[n][c][oh][ow] = max over the window's in-range elements of
+ * x[n][c][oh*s - p + i][ow*s - p + j], idx = the winner's h*W + w (see the
+ * scan rule above).  Ho = (H + 2p - kh)/s + 1, Wo likewise.  Returns -1 when a
+ * window can hold no in-range element (p >= kh or p >= kw) or sizes are bad. */
+OR_EXPORT int oracle_maxpool(const float* x, int64_t N, int64_t C, int64_t H, int64_t W, int32_t kh,
+                             int32_t kw, int32_t s, int32_t p, float* out, int32_t* idx) {
+  if (kh < 1 || kw < 1 || s < 1 || p < 0 || p >= kh || p >= kw) return -1;
+  if (H + 2 * p < kh || W + 2 * p < kw) return -1;
+  const int64_t Ho = (H + 2 * p - kh) / s + 1, Wo = (W + 2 * p - kw) / s + 1;
+  for (int64_t n = 0; n < N; ++n)
+    for (int64_t c = 0; c < C; ++c) {
+      const float* img = x + (n * C + c) * H * W;
+      float* dst = out + (n * C + c) * Ho * Wo;
+      int32_t* dix = idx + (n * C + c) * Ho * Wo;
+      for (int64_t oh = 0; oh < Ho; ++oh)
+        for (int64_t ow = 0; ow < Wo; ++ow) {
+          int have = 0;
+          float best = 0.0f;
+          int64_t at = -1;
+          for (int32_t i = 0; i < kh; ++i) {
+            const int64_t h = oh * s - p + i;
+            if (h < 0 || h >= H) continue;
+            for (int32_t j = 0; j < kw; ++j) {
+              const int64_t w = ow * s - p + j;
+              if (w < 0 || w >= W) continue;
+              const float v = img[h * W + w];
+              if (!have || v > best || isnan(v)) {
+                best = v;
+                at = h * W + w;
+                have = 1;
+              }
+            }
+          }
+          if (!have) return -1;
+          dst[oh * Wo + ow] = best;
+          dix[oh * Wo + ow] = (int32_t)at;
+        }
     }
   return 0;
 }

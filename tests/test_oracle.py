@@ -231,3 +231,88 @@ def test_upsample_ramp_closed_form():
 def test_upsample_identity_scale():
     x = inputs.normal_image((1, 2, 4, 5), seed=7)
     assert np.array_equal(oracle.upsample(x, 1), x.astype(np.float64))
+
+
+# ------------------------------------------------------------------- maxpool
+POOL_CASES = [((2, 3, 9, 11), (3, 3), 2, 1), ((1, 2, 8, 8), (2, 2), 2, 0), ((2, 1, 7, 5), (3, 2), 1, 1),
+              ((1, 4, 12, 10), (3, 3), 3, 0), ((3, 2, 5, 6), (1, 1), 1, 0), ((1, 1, 4, 13), (2, 3), 1, 1)]
+
+
+@pytest.mark.parametrize("shape,k,s,p", POOL_CASES)
+def test_maxpool_matches_torch_max_pool2d(shape, k, s, p):
+    # library routine: torch's CPU max pooling with indices (flat h*W + w)
+    x = inputs.normal_image(shape, seed=sum(shape) + s)
+    v, i = oracle.maxpool(x, k[0], k[1], s, p)
+    tv, ti = F.max_pool2d(torch.from_numpy(x), k, s, p, return_indices=True)
+    assert np.array_equal(v, tv.numpy()) and np.array_equal(i, ti.numpy().astype(np.int32))
+
+
+@pytest.mark.parametrize("shape,k,s,p", POOL_CASES)
+def test_maxpool_matches_sliding_window_max_and_first_argmax(shape, k, s, p):
+    # library routine: numpy sliding windows over a -inf padded copy; argmax
+    # returns the first maximum in row-major window order
+    x = inputs.normal_image(shape, seed=7 * sum(shape))
+    N, C, H, W = shape
+    xp = np.full((N, C, H + 2 * p, W + 2 * p), -np.inf, np.float32)
+    xp[:, :, p:p + H, p:p + W] = x
+    win = np.lib.stride_tricks.sliding_window_view(xp, k, axis=(2, 3))[:, :, ::s, ::s]
+    Ho, Wo = win.shape[2], win.shape[3]
+    flat = win.reshape(N, C, Ho, Wo, k[0] * k[1])
+    am = flat.argmax(-1)
+    hh = np.arange(Ho)[:, None] * s - p + am // k[1]
+    ww = np.arange(Wo)[None, :] * s - p + am % k[1]
+    v, i = oracle.maxpool(x, k[0], k[1], s, p)
+    assert np.array_equal(v, flat.max(-1)) and np.array_equal(i, (hh * W + ww).astype(np.int32))
+
+
+def test_maxpool_increasing_ramp_picks_last_valid_element():
+    # x = h*W + w grows along the scan, so each window's winner is its
+    # bottom-right in-range element, and value == index
+    N, C, H, W, k, s, p = 1, 1, 11, 9, 3, 2, 1
+    x = np.arange(H * W, dtype=np.float32).reshape(N, C, H, W)
+    v, i = oracle.maxpool(x, k, k, s, p)
+    Ho, Wo = v.shape[2:]
+    hb = np.minimum(np.arange(Ho) * s - p + k - 1, H - 1)[:, None]
+    wb = np.minimum(np.arange(Wo) * s - p + k - 1, W - 1)[None, :]
+    assert np.array_equal(i[0, 0], hb * W + wb) and np.array_equal(v[0, 0], (hb * W + wb).astype(np.float32))
+
+
+def test_maxpool_ties_keep_first_and_constant_windows():
+    # a constant image: every window ties, the winner is the top-left in-range element
+    H, W, k, s, p = 7, 8, 3, 2, 1
+    v, i = oracle.maxpool(np.full((1, 2, H, W), -1.5, np.float32), k, k, s, p)
+    Ho, Wo = v.shape[2:]
+    ht = np.maximum(np.arange(Ho) * s - p, 0)[:, None]
+    wt = np.maximum(np.arange(Wo) * s - p, 0)[None, :]
+    assert np.all(v == -1.5) and np.array_equal(i[0, 1], ht * W + wt)
+
+
+def test_maxpool_non_overlapping_equals_block_reshape_max():
+    x = inputs.normal_image((2, 3, 8, 12), seed=4)
+    v, i = oracle.maxpool(x, 2, 2, 2, 0)
+    blocks = x.reshape(2, 3, 4, 2, 6, 2)
+    assert np.array_equal(v, blocks.max(axis=(3, 5)))
+    np.testing.assert_array_equal(x.reshape(2, 3, -1)[np.arange(2)[:, None, None, None], np.arange(3)[None, :, None, None],
+                                                      i.astype(np.int64)], v)
+
+
+def test_maxpool_nan_propagates_and_minus_inf():
+    x = np.zeros((1, 1, 4, 4), np.float32)
+    x[0, 0, 1, 2] = np.nan
+    x[0, 0, 2, 3] = 5.0
+    x[0, 0, 3, 3] = np.nan
+    v, i = oracle.maxpool(x, 2, 2, 2, 0)
+    # window (0,1): NaN at (1,2) beats zeros; window (1,1): scan meets 5 then the NaN at (3,3)
+    assert np.isnan(v[0, 0, 0, 1]) and i[0, 0, 0, 1] == 1 * 4 + 2
+    assert np.isnan(v[0, 0, 1, 1]) and i[0, 0, 1, 1] == 3 * 4 + 3
+    assert v[0, 0, 0, 0] == 0 and i[0, 0, 0, 0] == 0
+    tv, ti = F.max_pool2d(torch.from_numpy(x), 2, 2, 0, return_indices=True)
+    assert np.array_equal(np.isnan(v), np.isnan(tv.numpy())) and np.array_equal(i, ti.numpy())
+    y = np.full((1, 1, 3, 3), -np.inf, np.float32)
+    v, i = oracle.maxpool(y, 3, 3, 1, 1)
+    assert np.all(v == -np.inf) and np.array_equal(i[0, 0], [[0, 0, 1], [0, 0, 1], [3, 3, 4]])
+
+
+def test_maxpool_rejects_windows_with_no_input():
+    with pytest.raises(ValueError):
+        oracle.maxpool(np.zeros((1, 1, 4, 4), np.float32), 2, 2, 1, 2)
