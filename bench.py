@@ -3,8 +3,10 @@
 Default workload (the memory + compute pair): batch-norm statistics of an fp32
 NCHW tensor [64, 256, 56, 56] (x = z*scale_c + shift_c) fused with 128 rounds of
 integer mixing over 2^24 uint32 seeds.  ``--workload`` selects one of the
-memory + atomic pairs instead: im2col [32,128,56,56] 3x3/s1/p1 or bilinear x2
-upsample [32,64,128,128], each with a 256-bin histogram of 2^26 Zipf bytes.
+memory + atomic pairs instead: im2col [32,128,56,56] 3x3/s1/p1, bilinear x2
+upsample [32,64,128,128] or 3x3/s2/p1 max pooling with indices over the
+ResNet-stem activations [64,64,112,112], each with a 256-bin histogram of 2^26
+Zipf bytes.
 
 A step is one fused launch of the pair at the configuration the exhaustive
 tuner picks (split, workgroup size, VGPR bound); the same inputs are also run
@@ -32,7 +34,7 @@ METRIC = "fused vs back-to-back time speedup (%) per pair at 1 MI355X; HBM GB/s 
 INT_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
 OPS_PER_ROUND = 8  # 3 shifts, 3 xors, 1 multiply, 1 add
-WORKLOADS = ("bn_stats+int_mix", "im2col+lds_hist", "upsample+lds_hist")
+WORKLOADS = ("bn_stats+int_mix", "im2col+lds_hist", "upsample+lds_hist", "maxpool+lds_hist")
 
 
 def parse():
@@ -119,7 +121,7 @@ class Workload:
                 self.ta = H.task_im2col(xd, o, 3, 3, 1, 1)
                 self.desc = "im2col fp32 [32,128,56,56] 3x3/s1/p1 + lds_hist 2^26 Zipf(1.2) bytes"
                 self.kernel = "fused_cap/fused_nocap<Im2col,LdsHist>"
-            else:
+            elif name == "upsample+lds_hist":
                 self.shape = (32, 64, 128, 128)
                 self.x = inputs.normal_image(self.shape, 3)
                 xd = torch.from_numpy(self.x).cuda()
@@ -127,10 +129,22 @@ class Workload:
                 self.ta = H.task_upsample(xd, o, 2)
                 self.desc = "upsample x2 fp32 [32,64,128,128] + lds_hist 2^26 Zipf(1.2) bytes"
                 self.kernel = "fused_cap/fused_nocap<LdsHist,Upsample>"
+            else:
+                self.shape = (64, 64, 112, 112)
+                self.x = inputs.normal_image(self.shape, 4)
+                xd = torch.from_numpy(self.x).cuda()
+                oshape = H.maxpool_out_shape(self.shape, 3, 3, 2, 1)
+                o = torch.empty(oshape, device="cuda")
+                oi = torch.empty(oshape, dtype=torch.int32, device="cuda")
+                self.ta = H.task_maxpool(xd, o, oi, 3, 3, 2, 1)
+                self.desc = ("maxpool 3x3/s2/p1 fp32 [64,64,112,112] with int32 indices + lds_hist 2^26 "
+                             "Zipf(1.2) bytes")
+                self.kernel = "fused_cap/fused_nocap<LdsHist,Maxpool>"
             self.tb = H.task_lds_hist(hd, counts)
-            self.outs = [o, counts]
+            pool = name == "maxpool+lds_hist"
+            self.outs = [o, oi, counts] if pool else [o, counts]
             self.bufs = [xd, hd]
-            self.alg_bytes = self.x.nbytes + o.numel() * 4 + self.hist.nbytes + 1024
+            self.alg_bytes = self.x.nbytes + o.numel() * (8 if pool else 4) + self.hist.nbytes + 1024
             self.alg_ops = 0
             self.bound = "hbm"
         self.pair = H.make_pair(self.ta, self.tb)
@@ -148,8 +162,10 @@ class Workload:
         else:
             if self.name == "im2col+lds_hist":
                 oracle.im2col(self.x, 3, 3, 1, 1)
-            else:
+            elif self.name == "upsample+lds_hist":
                 oracle.upsample(self.x, 2)
+            else:
+                oracle.maxpool(self.x, 3, 3, 2, 1)
             t1 = time.perf_counter()
             oracle.hist256(self.hist)
             parts = self.desc

@@ -63,13 +63,15 @@ typedef enum {
   HF_IM2COL = 2,    /* image patches -> columns, unfold layout, zero padding         */
   HF_LDS_HIST = 3,  /* 256-bin histogram of uint8 values (bin = byte value)          */
   HF_UPSAMPLE = 4,  /* bilinear upsampling by an integer factor, half-pixel centres  */
-  HF_NUM_KINDS = 5
+  HF_MAXPOOL = 5,   /* 2-D max pooling with the winner's flat index (Sec. IV-A)      */
+  HF_NUM_KINDS = 6
 } hf_kind;
 
 /* One kernel instance.
  *   kind         hf_kind
  *   in           device input
- *                  BN_STATS, IM2COL, UPSAMPLE : float  [n][c][h][w], contiguous
+ *                  BN_STATS, IM2COL, UPSAMPLE,
+ *                  MAXPOOL                    : float  [n][c][h][w], contiguous
  *                  INT_MIX                    : uint32 [n]
  *                  LDS_HIST                   : uint8  [n]
  *   out0         device output
@@ -78,13 +80,23 @@ typedef enum {
  *                  IM2COL   : float [n][c*kh*kw][Ho*Wo], Ho=(h+2*pad-kh)/stride+1 (same for Wo)
  *                  LDS_HIST : uint32 counts[256] (overwritten, not accumulated)
  *                  UPSAMPLE : float [n][c][h*s][w*s]
- *   out1         BN_STATS: float var[c] (biased, divided by n*h*w); unused otherwise
+ *                  MAXPOOL  : float [n][c][Ho][Wo], Ho=(h+2*pad-kh)/stride+1 (same for Wo):
+ *                             the maximum over the window's in-range elements
+ *   out1         BN_STATS: float var[c] (biased, divided by n*h*w)
+ *                MAXPOOL : int32 [n][c][Ho][Wo] flat index y*w + x, within its
+ *                          input plane, of the element each maximum came from
+ *                          (row-major scan of the window; a later element wins
+ *                          only if greater or NaN, so ties keep the first and
+ *                          a NaN propagates), or NULL to skip the indices
+ *                unused otherwise
  *   scratch      optional caller scratch (see conventions above), or NULL
  *   n,c,h,w      shape; INT_MIX and LDS_HIST use n as the element count only
  *   p[4]         INT_MIX : p[0] = rounds R >= 0
  *                IM2COL  : p[0]=kh, p[1]=kw, p[2]=stride, p[3]=pad
  *                LDS_HIST: p[0] = number of bins, must be 256
  *                UPSAMPLE: p[0] = integer scale s in [1, 16]
+ *                MAXPOOL : p[0]=kh, p[1]=kw, p[2]=stride, p[3]=pad with
+ *                          0 <= pad < min(kh, kw) (padded positions never win)
  * Input and output buffers must be 4-byte aligned (LDS_HIST input: any) and must
  * not overlap.  Element counts must stay below 2^31 per buffer. */
 typedef struct {
@@ -247,7 +259,7 @@ int hf_register_bound(int d1, int d2, int vgpr_a, int vgpr_b, int lds_fused);
  * used.  Trained and evaluated on the GPU by the library's own kernels.  One
  * model per process, on the device current at hf_mlp_init.  Unless stated
  * otherwise, arrays are HOST pointers, row-major. */
-#define HF_MLP_FEATURES 32
+#define HF_MLP_FEATURES 34 /* 2 * (HF_NUM_KINDS + 7) + 8; the last is log2(sum of solo times) */
 /* Allocates the model for d_in features: He-uniform weights from `seed`
  * (splitmix64), zero biases, identity feature standardisation. */
 int hf_mlp_init(int d_in, uint64_t seed);

@@ -32,7 +32,7 @@ from . import inputs
 
 def draw(count: int = 1000, seed: int = 3, kmin: int = 12, kmax: int = 18):
     g = inputs.rng(seed)
-    kinds = g.integers(0, 5, size=count)
+    kinds = g.integers(0, len(H.KIND_NAMES), size=count)
     logs = g.integers(kmin, kmax + 1, size=count)
     groups, gid, i = [], 0, 0
     while i < count:
@@ -54,7 +54,7 @@ class Workload:
         for i, (kind, k) in enumerate(zip(kinds, logs)):
             n = 1 << k
             s = seed * 100000 + i
-            if kind in (H.HF_BN_STATS, H.HF_IM2COL, H.HF_UPSAMPLE):
+            if kind in (H.HF_BN_STATS, H.HF_IM2COL, H.HF_UPSAMPLE, H.HF_MAXPOOL):
                 x = inputs.cuda_normal((1, 16, 16, n // 256), s)
                 if kind == H.HF_BN_STATS:
                     o = [torch.empty(16, device="cuda"), torch.empty(16, device="cuda")]
@@ -62,9 +62,13 @@ class Workload:
                 elif kind == H.HF_IM2COL:
                     o = [torch.empty((1, 16 * 9, 16 * (n // 256)), device="cuda")]
                     t = H.task_im2col(x, o[0], 3, 3, 1, 1)
-                else:
+                elif kind == H.HF_UPSAMPLE:
                     o = [torch.empty((1, 16, 32, 2 * (n // 256)), device="cuda")]
                     t = H.task_upsample(x, o[0], 2)
+                else:
+                    osh = H.maxpool_out_shape(tuple(x.shape), 3, 3, 2, 1)
+                    o = [torch.empty(osh, device="cuda"), torch.empty(osh, dtype=torch.int32, device="cuda")]
+                    t = H.task_maxpool(x, o[0], o[1], 3, 3, 2, 1)
             elif kind == H.HF_INT_MIX:
                 x = inputs.cuda_uint32(n, s)
                 o = [torch.empty_like(x)]

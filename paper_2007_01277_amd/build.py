@@ -25,7 +25,8 @@ FLAGS = [
     "-Wno-unused-command-line-argument",
 ]
 
-PAIRS = [(a, b) for a in range(5) for b in range(a, 5)]
+NUM_KINDS = 6
+PAIRS = [(a, b) for a in range(NUM_KINDS) for b in range(a, NUM_KINDS)]
 
 
 def _units():

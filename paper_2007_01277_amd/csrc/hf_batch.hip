@@ -49,6 +49,7 @@ __device__ __forceinline__ void run_body(int kind, const DevTask& t, const Part&
     case HF_IM2COL: Im2col::run(t, p, bar, lds); break;
     case HF_LDS_HIST: LdsHist::run(t, p, bar, lds); break;
     case HF_UPSAMPLE: Upsample::run(t, p, bar, lds); break;
+    case HF_MAXPOOL: Maxpool::run(t, p, bar, lds); break;
     default: break;
   }
 }
@@ -152,6 +153,13 @@ static double est_cost_us(const hf_task* t) {
       const double s2 = (double)t->p[0] * t->p[0];
       bytes = 4 * n * c * h * w * (1 + s2);
       ops = 20 * n * c * h * w * s2;
+      break;
+    }
+    case HF_MAXPOOL: {
+      const double kh = t->p[0], kw = t->p[1], s = t->p[2], p = t->p[3];
+      const double out = n * c * (std::floor((h + 2 * p - kh) / s) + 1) * (std::floor((w + 2 * p - kw) / s) + 1);
+      bytes = 4 * n * c * h * w + (t->out1 ? 8 : 4) * out;
+      ops = 4 * kh * kw * out;
       break;
     }
   }

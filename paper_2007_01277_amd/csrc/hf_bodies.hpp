@@ -73,12 +73,23 @@ struct UpArgs {  // bilinear upsampling by integer factor s, half-pixel centres
   FastDiv div_ho, div_row;  // div_row: by Wo4 (vector) or Wo
 };
 
+struct PoolArgs {  // max pooling with the winner's flat index
+  const float* x;
+  float* out;
+  int32_t* idx;  // null: values only
+  uint32_t H, W, Ho, Wo, kh, kw, s, p;
+  uint32_t total;  // N*C*Ho*Wo outputs
+  uint32_t units;  // ceil(total / Maxpool::kUnit)
+  FastDiv div_plane, div_wo;  // by Ho*Wo and by Wo
+};
+
 union DevTask {
   BnArgs bn;
   MixArgs mix;
   HistArgs hist;
   Im2colArgs im2col;
   UpArgs up;
+  PoolArgs pool;
 };
 
 // Agent-scope helpers for partial results exchanged between workgroups.
@@ -578,6 +589,92 @@ struct Upsample {
         }
       }
     }
+  }
+};
+
+// =================================================================== maxpool
+// 2-D max pooling (Sec. IV-A "Maxpool").  A unit is kUnit consecutive outputs
+// of the flattened [N][C][Ho][Wo] output, kPer per lane (lane l takes outputs
+// l, l + 64, ...).  Each wavefront owns a contiguous, balanced range of units,
+// so the input rows shared by vertically adjacent windows are re-read from the
+// caches of the same CU.
+//
+// Window coordinates are clamped into the image instead of being skipped: with
+// pad < kh, kw a clamped row or column is always inside the window, and it is
+// met in the scan before (low side) or after (high side) the real copy of the
+// same element, never between two other elements, so under the scan rule (a
+// later element wins only if greater or NaN) the winner and its index are
+// exactly those of the unclamped scan.  All loads are therefore unconditional.
+struct Maxpool {
+  static constexpr uint32_t kPer = 2;
+  static constexpr uint32_t kUnit = 64 * kPer;
+  static constexpr uint32_t lds_words(int) { return 0; }
+
+  __device__ static __forceinline__ int32_t clampi(int32_t v, int32_t hi) { return min(max(v, 0), hi); }
+
+  template <int KH, int KW>
+  __device__ static __forceinline__ void window(const PoolArgs& a, const float* img, int32_t h0, int32_t w0,
+                                                uint32_t kh, uint32_t kw, float& best, int32_t& at) {
+    const int32_t Hm = (int32_t)a.H - 1, Wm = (int32_t)a.W - 1, W = (int32_t)a.W;
+    const uint32_t nh = KH > 0 ? (uint32_t)KH : kh, nw = KW > 0 ? (uint32_t)KW : kw;
+    best = 0.f;
+    at = -1;
+#pragma unroll
+    for (uint32_t i = 0; i < nh; ++i) {
+      const int32_t h = clampi(h0 + (int32_t)i, Hm);
+#pragma unroll
+      for (uint32_t j = 0; j < nw; ++j) {
+        const int32_t e = h * W + clampi(w0 + (int32_t)j, Wm);
+        const float v = img[e];
+        if ((i == 0 && j == 0) || v > best || __builtin_isnan(v)) {
+          best = v;
+          at = e;
+        }
+      }
+    }
+  }
+
+  template <int KH, int KW>
+  __device__ static __forceinline__ void units(const PoolArgs& a, uint32_t ubeg, uint32_t uend, uint32_t lane) {
+    const uint32_t plane_sz = a.H * a.W;
+    for (uint32_t u = ubeg; u < uend; ++u) {
+#pragma unroll
+      for (uint32_t t = 0; t < kPer; ++t) {
+        const uint32_t o = u * kUnit + lane + 64u * t;
+        const uint32_t oc = min(o, a.total - 1u);  // lanes past the end redo the last output
+        const uint32_t plane = fdiv(oc, a.div_plane);
+        const uint32_t r = oc - plane * a.div_plane.d;
+        const uint32_t oh = fdiv(r, a.div_wo);
+        const uint32_t ow = r - oh * a.Wo;
+        const float* img = a.x + (size_t)plane * plane_sz;
+        float best;
+        int32_t at;
+        window<KH, KW>(a, img, (int32_t)(oh * a.s) - (int32_t)a.p, (int32_t)(ow * a.s) - (int32_t)a.p, a.kh,
+                       a.kw, best, at);
+        if (o < a.total) {
+          __builtin_nontemporal_store(best, a.out + o);
+          if (a.idx) __builtin_nontemporal_store(at, a.idx + o);
+        }
+      }
+    }
+  }
+
+  template <class Bar>
+  __device__ static void run(const DevTask& dt, const Part& p, Bar&, uint32_t*) {
+    const PoolArgs& a = dt.pool;
+    const uint32_t lane = lane_id();
+    const uint32_t nw = p.nwg * p.nwaves;
+    const uint32_t gw = p.wg * p.nwaves + p.wave;
+    const uint32_t q = a.units / nw, r = a.units - q * nw;
+    const uint32_t ubeg = gw * q + min(gw, r);
+    const uint32_t uend = ubeg + q + (gw < r ? 1u : 0u);
+    if (ubeg >= uend) return;
+    if (a.kh == 3 && a.kw == 3)
+      units<3, 3>(a, ubeg, uend, lane);
+    else if (a.kh == 2 && a.kw == 2)
+      units<2, 2>(a, ubeg, uend, lane);
+    else
+      units<0, 0>(a, ubeg, uend, lane);
   }
 };
 

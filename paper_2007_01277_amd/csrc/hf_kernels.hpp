@@ -23,6 +23,7 @@ template <> struct BodyOf<1> { using T = IntMix; };
 template <> struct BodyOf<2> { using T = Im2col; };
 template <> struct BodyOf<3> { using T = LdsHist; };
 template <> struct BodyOf<4> { using T = Upsample; };
+template <> struct BodyOf<5> { using T = Maxpool; };
 
 constexpr uint32_t max1(uint32_t v) { return v ? v : 1u; }
 

@@ -304,6 +304,13 @@ static void alg_work(const hf_task* t, double* bytes, double* ops) {
       *ops = 20.0 * out;
       break;
     }
+    case HF_MAXPOOL: {
+      const double kh = t->p[0], kw = t->p[1], s = t->p[2], p = t->p[3];
+      const double out = n * c * (std::floor((h + 2 * p - kh) / s) + 1) * (std::floor((w + 2 * p - kw) / s) + 1);
+      *bytes = 4.0 * n * c * h * w + (t->out1 ? 8.0 : 4.0) * out;
+      *ops = 4.0 * kh * kw * out;
+      break;
+    }
   }
 }
 
@@ -339,14 +346,18 @@ static int solo_feat(DeviceState* s, const hf_task* t, hipStream_t st, SoloFeat*
 
 // Features of one candidate (kFeat values), kernels in canonical order (the
 // smaller kind first; the split fraction refers to that kernel):
-//   per kernel (12 each): one-hot kind (5); log2 solo time at
-//   blocks 256, 512, 1024; log2 algorithmic MB and mega-lane-ops; fractions of
-//   the HBM and integer-ALU peaks the best solo run reached;
+//   per kernel (kPerKernel each): one-hot kind (HF_NUM_KINDS); log2 solo time
+//   at blocks 256, 512, 1024; log2 algorithmic MB and mega-lane-ops; fractions
+//   of the HBM and integer-ALU peaks the best solo run reached;
 //   configuration (8): split fraction s = 64*split_waves/block; log2(block/512);
 //   VGPR bound / 128 (1 when unbounded); resident waves per SIMD / 8;
 //   log2(t_a(block)/s), log2(t_b(block)/(1-s)) and the log2 of their maximum,
 //   with t_k(block) the solo time at the candidate's block size; log2 of the
-//   sum of the best solo times.
+//   sum of the best solo times (the last feature).
+constexpr int kPerKernel = HF_NUM_KINDS + 7;
+constexpr int kCfg = 2 * kPerKernel;
+static_assert(kCfg + 8 == kFeat, "feature layout and HF_MLP_FEATURES disagree");
+
 static void fill_features(const SoloFeat& fa0, const SoloFeat& fb0, const hf_config& c, int waves_per_simd,
                           float* x) {
   auto l2 = [](double v) { return (float)std::log2(std::max(v, 1e-30)); };
@@ -358,28 +369,30 @@ static void fill_features(const SoloFeat& fa0, const SoloFeat& fb0, const hf_con
   const SoloFeat& fb = swap ? fa0 : fb0;
   const SoloFeat* f[2] = {&fa, &fb};
   for (int k = 0; k < 2; ++k) {
-    float* o = x + 12 * k;
-    for (int i = 0; i < 5; ++i) o[i] = (f[k]->kind == i) ? 1.f : 0.f;
-    o[5] = l2(f[k]->t_blk[0]);
-    o[6] = l2(f[k]->t_blk[1]);
-    o[7] = l2(f[k]->t_blk[2]);
-    o[8] = l2(f[k]->bytes / 1e6 + 1e-3);
-    o[9] = l2(f[k]->ops / 1e6 + 1e-3);
-    o[10] = (float)(f[k]->bytes / (f[k]->t_ms * 1e-3) / 8e12);
-    o[11] = (float)(f[k]->ops / (f[k]->t_ms * 1e-3) / 39.3216e12);
+    float* o = x + kPerKernel * k;
+    for (int i = 0; i < HF_NUM_KINDS; ++i) o[i] = (f[k]->kind == i) ? 1.f : 0.f;
+    float* q = o + HF_NUM_KINDS;
+    q[0] = l2(f[k]->t_blk[0]);
+    q[1] = l2(f[k]->t_blk[1]);
+    q[2] = l2(f[k]->t_blk[2]);
+    q[3] = l2(f[k]->bytes / 1e6 + 1e-3);
+    q[4] = l2(f[k]->ops / 1e6 + 1e-3);
+    q[5] = (float)(f[k]->bytes / (f[k]->t_ms * 1e-3) / 8e12);
+    q[6] = (float)(f[k]->ops / (f[k]->t_ms * 1e-3) / 39.3216e12);
   }
   const int bi = c.block == 256 ? 0 : (c.block == 512 ? 1 : 2);
   const double W = c.block / 64.0;
   const double s = swap ? 1.0 - c.split_waves / W : c.split_waves / W;
-  x[24] = (float)s;
-  x[25] = l2(c.block / 512.0);
-  x[26] = c.vgpr_cap == 0 ? 1.f : c.vgpr_cap / 128.f;
-  x[27] = waves_per_simd / 8.f;
+  float* g = x + kCfg;
+  g[0] = (float)s;
+  g[1] = l2(c.block / 512.0);
+  g[2] = c.vgpr_cap == 0 ? 1.f : c.vgpr_cap / 128.f;
+  g[3] = waves_per_simd / 8.f;
   const double ta = fa.t_blk[bi] / s, tb = fb.t_blk[bi] / (1.0 - s);
-  x[28] = l2(ta);
-  x[29] = l2(tb);
-  x[30] = l2(std::max(ta, tb));
-  x[31] = l2(fa.t_ms + fb.t_ms);
+  g[4] = l2(ta);
+  g[5] = l2(tb);
+  g[6] = l2(std::max(ta, tb));
+  g[7] = l2(fa.t_ms + fb.t_ms);
 }
 
 int featurize(DeviceState* s, const hf_pair* pr, const hf_config* cfg, int n, hipStream_t st, float* X) {

@@ -25,9 +25,11 @@ int record_hip(hipError_t e) {
 // ------------------------------------------------------------------ registry
 #define HF_DECLARE_TABLE(KA, KB) const KernelEntry* hf_table_##KA##_##KB(int* count);
 HF_DECLARE_TABLE(0, 0) HF_DECLARE_TABLE(0, 1) HF_DECLARE_TABLE(0, 2) HF_DECLARE_TABLE(0, 3)
-HF_DECLARE_TABLE(0, 4) HF_DECLARE_TABLE(1, 1) HF_DECLARE_TABLE(1, 2) HF_DECLARE_TABLE(1, 3)
-HF_DECLARE_TABLE(1, 4) HF_DECLARE_TABLE(2, 2) HF_DECLARE_TABLE(2, 3) HF_DECLARE_TABLE(2, 4)
-HF_DECLARE_TABLE(3, 3) HF_DECLARE_TABLE(3, 4) HF_DECLARE_TABLE(4, 4)
+HF_DECLARE_TABLE(0, 4) HF_DECLARE_TABLE(0, 5) HF_DECLARE_TABLE(1, 1) HF_DECLARE_TABLE(1, 2)
+HF_DECLARE_TABLE(1, 3) HF_DECLARE_TABLE(1, 4) HF_DECLARE_TABLE(1, 5) HF_DECLARE_TABLE(2, 2)
+HF_DECLARE_TABLE(2, 3) HF_DECLARE_TABLE(2, 4) HF_DECLARE_TABLE(2, 5) HF_DECLARE_TABLE(3, 3)
+HF_DECLARE_TABLE(3, 4) HF_DECLARE_TABLE(3, 5) HF_DECLARE_TABLE(4, 4) HF_DECLARE_TABLE(4, 5)
+HF_DECLARE_TABLE(5, 5)
 const KernelEntry* hf_table_solo(int* count);
 
 static std::vector<KernelEntry>& registry() {
@@ -35,9 +37,10 @@ static std::vector<KernelEntry>& registry() {
   static std::once_flag once;
   std::call_once(once, [] {
     const KernelEntry* (*tabs[])(int*) = {
-        hf_table_0_0, hf_table_0_1, hf_table_0_2, hf_table_0_3, hf_table_0_4,
-        hf_table_1_1, hf_table_1_2, hf_table_1_3, hf_table_1_4, hf_table_2_2,
-        hf_table_2_3, hf_table_2_4, hf_table_3_3, hf_table_3_4, hf_table_4_4, hf_table_solo};
+        hf_table_0_0, hf_table_0_1, hf_table_0_2, hf_table_0_3, hf_table_0_4, hf_table_0_5,
+        hf_table_1_1, hf_table_1_2, hf_table_1_3, hf_table_1_4, hf_table_1_5, hf_table_2_2,
+        hf_table_2_3, hf_table_2_4, hf_table_2_5, hf_table_3_3, hf_table_3_4, hf_table_3_5,
+        hf_table_4_4, hf_table_4_5, hf_table_5_5, hf_table_solo};
     for (auto f : tabs) {
       int n = 0;
       const KernelEntry* e = f(&n);
@@ -199,6 +202,21 @@ int validate_task(const hf_task* t) {
       if (!aligned(t->in, 4) || !aligned(t->out0, 4)) return HF_EINVAL;
       return HF_OK;
     }
+    case HF_MAXPOOL: {
+      const int kh = t->p[0], kw = t->p[1], s = t->p[2], p = t->p[3];
+      if (kh < 1 || kw < 1 || s < 1 || kh > 64 || kw > 64 || s > 64) return HF_EINVAL;
+      if (p < 0 || p >= kh || p >= kw) return HF_EINVAL;  // every window holds an input element
+      if (t->c < 1 || t->h < 1 || t->w < 1) return HF_EINVAL;
+      if (t->h + 2 * p < kh || t->w + 2 * p < kw) return HF_EINVAL;
+      const int64_t Ho = (t->h + 2 * p - kh) / s + 1, Wo = (t->w + 2 * p - kw) / s + 1;
+      if (t->n > 0) {
+        if (!t->in || !t->out0) return HF_EINVAL;
+        if (t->n > kMaxElems / t->c / t->h / t->w) return HF_EINVAL;
+        if (t->n > kMaxElems / t->c / Ho / Wo) return HF_EINVAL;
+      }
+      if (!aligned(t->in, 4) || !aligned(t->out0, 4) || !aligned(t->out1, 4)) return HF_EINVAL;
+      return HF_OK;
+    }
   }
   return HF_EINVAL;
 }
@@ -311,6 +329,25 @@ int prepare(const hf_task* t, void* scratch, DevTask* dt) {
       a.div_row = make_fastdiv(rowlen);
       return HF_OK;
     }
+    case HF_MAXPOOL: {
+      PoolArgs& a = dt->pool;
+      a.x = static_cast<const float*>(t->in);
+      a.out = static_cast<float*>(t->out0);
+      a.idx = static_cast<int32_t*>(t->out1);
+      a.H = (uint32_t)t->h;
+      a.W = (uint32_t)t->w;
+      a.kh = (uint32_t)t->p[0];
+      a.kw = (uint32_t)t->p[1];
+      a.s = (uint32_t)t->p[2];
+      a.p = (uint32_t)t->p[3];
+      a.Ho = (a.H + 2 * a.p - a.kh) / a.s + 1;
+      a.Wo = (a.W + 2 * a.p - a.kw) / a.s + 1;
+      a.total = (uint32_t)t->n * (uint32_t)t->c * a.Ho * a.Wo;
+      a.units = (a.total + Maxpool::kUnit - 1u) / Maxpool::kUnit;
+      a.div_plane = make_fastdiv(a.Ho * a.Wo);
+      a.div_wo = make_fastdiv(a.Wo);
+      return HF_OK;
+    }
   }
   return HF_EINVAL;
 }
@@ -326,6 +363,7 @@ int64_t useful_wgs(const hf_task* t, const DevTask& d, int waves) {
     case HF_LDS_HIST: units = cdiv(std::max<uint32_t>(d.hist.n16, 1), 64 * waves); break;
     case HF_IM2COL: units = cdiv(d.im2col.units, waves); break;
     case HF_UPSAMPLE: units = cdiv(d.up.units, waves); break;
+    case HF_MAXPOOL: units = cdiv(d.pool.units, waves); break;
   }
   return std::max<int64_t>(units, 1);
 }

@@ -14,8 +14,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("HFUSE_LIB") or os.path.join(PKG, "libhfuse.so")
 
 HF_OK, HF_EINVAL, HF_EUNSUPPORTED, HF_EHIP, HF_ETIMEOUT, HF_ENOMEM, HF_ENOMODEL = 0, -1, -2, -3, -4, -5, -6
-HF_BN_STATS, HF_INT_MIX, HF_IM2COL, HF_LDS_HIST, HF_UPSAMPLE = range(5)
-KIND_NAMES = ["bn_stats", "int_mix", "im2col", "lds_hist", "upsample"]
+HF_BN_STATS, HF_INT_MIX, HF_IM2COL, HF_LDS_HIST, HF_UPSAMPLE, HF_MAXPOOL = range(6)
+KIND_NAMES = ["bn_stats", "int_mix", "im2col", "lds_hist", "upsample", "maxpool"]
 HF_SERIAL, HF_STREAMS = 0, 1
 HF_TUNE_EXHAUSTIVE, HF_TUNE_PAPER, HF_TUNE_NAIVE, HF_TUNE_MLP = range(4)
 CAPS = (0, 64, 80, 96, 128)
@@ -206,6 +206,22 @@ def task_upsample(x, out, scale: int) -> hf_task:
     return t
 
 
+def task_maxpool(x, out, idx=None, kh: int = 3, kw: int = 3, stride: int = 2, pad: int = 1) -> hf_task:
+    """Max pooling of `x` into `out`; `idx` (int32, optional) receives each
+    maximum's flat index h*W + w within its input plane."""
+    t = hf_task()
+    t.kind = HF_MAXPOOL
+    t.p[0], t.p[1], t.p[2], t.p[3] = kh, kw, stride, pad
+    t.in_, t.out0, t.out1 = _ptr(x), _ptr(out), _ptr(idx)
+    t.n, t.c, t.h, t.w = x.shape
+    return t
+
+
+def maxpool_out_shape(shape, kh=3, kw=3, stride=2, pad=1):
+    n, c, h, w = shape
+    return (n, c, (h + 2 * pad - kh) // stride + 1, (w + 2 * pad - kw) // stride + 1)
+
+
 def make_pair(a: hf_task, b: hf_task) -> hf_pair:
     return hf_pair(a, b)
 
@@ -312,7 +328,7 @@ def hf_register_bound(d1: int, d2: int, vgpr_a: int, vgpr_b: int, lds_fused: int
 
 
 # ------------------------------------------------------------------ learned cost model
-MLP_FEATURES = 32
+MLP_FEATURES = 2 * (len(KIND_NAMES) + 7) + 8  # HF_MLP_FEATURES
 
 
 def _f32(a):

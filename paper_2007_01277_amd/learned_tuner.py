@@ -1,6 +1,6 @@
 """Learned tuner: sample collection, training and regret against the exhaustive search.
 
-Workload: random pairs of two distinct kinds drawn from the five kernels, each
+Workload: random pairs of two distinct kinds drawn from the six kernels, each
 of 2^k elements with k uniform in [16, 26] (image kinds as [2^k / 65536, 64, 32,
 32], integer mixing with 32 rounds, histogram bytes from the Zipf law).  For
 every pair the tuner's own profiler times every candidate of the exhaustive
@@ -39,7 +39,7 @@ def draw_pairs(n_pairs: int, seed: int = 2, kmin: int = 16, kmax: int = 26):
     g = inputs.rng(seed)
     out = []
     for _ in range(n_pairs):
-        a, b = g.choice(5, size=2, replace=False)
+        a, b = g.choice(len(H.KIND_NAMES), size=2, replace=False)
         ka, kb = g.integers(kmin, kmax + 1, size=2)
         out.append((int(a), int(b), int(ka), int(kb)))
     return out
@@ -53,7 +53,7 @@ class Instance:
         import torch
         n = 1 << k
         self.bufs = []
-        if kind in (H.HF_BN_STATS, H.HF_IM2COL, H.HF_UPSAMPLE):
+        if kind in (H.HF_BN_STATS, H.HF_IM2COL, H.HF_UPSAMPLE, H.HF_MAXPOOL):
             N = n // 65536
             x = inputs.cuda_normal((N,) + IMAGE, seed)
             self.bufs.append(x)
@@ -65,10 +65,15 @@ class Instance:
                 o = torch.empty((N, IMAGE[0] * 9, IMAGE[1] * IMAGE[2]), device="cuda")
                 self.bufs.append(o)
                 self.task = H.task_im2col(x, o, 3, 3, 1, 1)
-            else:
+            elif kind == H.HF_UPSAMPLE:
                 o = torch.empty((N, IMAGE[0], 2 * IMAGE[1], 2 * IMAGE[2]), device="cuda")
                 self.bufs.append(o)
                 self.task = H.task_upsample(x, o, 2)
+            else:
+                osh = H.maxpool_out_shape((N,) + IMAGE, 3, 3, 2, 1)
+                o, oi = torch.empty(osh, device="cuda"), torch.empty(osh, dtype=torch.int32, device="cuda")
+                self.bufs += [o, oi]
+                self.task = H.task_maxpool(x, o, oi, 3, 3, 2, 1)
         elif kind == H.HF_INT_MIX:
             s = inputs.cuda_uint32(n, seed)
             o = torch.empty_like(s)
@@ -117,7 +122,7 @@ def collect(pairs, reps: int = 10, seed: int = 2, log=sys.stderr):
             "cands": keys, "pairs": pairs}
 
 
-SUM_SOLO = 31  # feature index of log2(sum of the best solo times)
+SUM_SOLO = H.MLP_FEATURES - 1  # feature index of log2(sum of the best solo times)
 
 
 def evaluate(data, folds: int = 4, per_pair: int = 14, topk: int = 3, epochs: int = 500,

@@ -3,6 +3,8 @@ check of its outputs against the CPU oracle.
 
 Tolerances (written here, used by every GPU test):
   * integer and copy kernels (int_mix, lds_hist, im2col): bit-exact;
+  * maxpool: bit-exact values (NaN where the oracle has NaN) and indices, since
+    a maximum is one of its inputs;
   * bn_stats: |d mean| <= 1e-5 * (|mean| + sigma) and |d var| <= 1e-5 * var
     (a relative bound on the mean alone is ill-posed when the mean is ~0);
   * upsample: |d out| <= 1e-5 * sum_k |w_k x_k| over the four taps.
@@ -139,6 +141,27 @@ def up_case(shape, scale=2, seed=0, check_slice=None) -> Case:
     return Case(t, {"in": xd, "outs": [out]}, check, f"upsample{tuple(shape)}x{scale}")
 
 
+def pool_case(shape, k=(3, 3), s=2, p=1, seed=0, offset=0, with_idx=True, x=None, check_images=None) -> Case:
+    xh = inputs.normal_image(shape, seed) if x is None else x
+    xd = dev(xh, offset)
+    oshape = H.maxpool_out_shape(shape, k[0], k[1], s, p)
+    out = torch.full(oshape, 7.0, device=DEV)
+    idx = torch.full(oshape, 7, dtype=torch.int32, device=DEV) if with_idx else None
+    t = H.task_maxpool(xd, out, idx, k[0], k[1], s, p)
+
+    def check(outs):
+        imgs = range(shape[0]) if check_images is None else check_images
+        for i in imgs:
+            v, ix = oracle.maxpool(xh[i:i + 1], k[0], k[1], s, p)
+            got = outs[0][i:i + 1].cpu().numpy()
+            assert np.array_equal(got, v, equal_nan=True), f"values of image {i}"
+            if with_idx:
+                assert np.array_equal(outs[1][i:i + 1].cpu().numpy(), ix), f"indices of image {i}"
+
+    outs = [out] if idx is None else [out, idx]
+    return Case(t, {"in": xd, "outs": outs}, check, f"maxpool{tuple(shape)}k{k}s{s}p{p}+{offset}")
+
+
 def small_cases(kind, seed=0):
     """Small cases of one kind covering several tiles and a ragged tail."""
     if kind == H.HF_BN_STATS:
@@ -152,6 +175,9 @@ def small_cases(kind, seed=0):
                 im2col_case((1, 4, 6, 7), (2, 3), 1, 0, seed)]
     if kind == H.HF_UPSAMPLE:
         return [up_case((2, 8, 16, 16), 2, seed), up_case((1, 3, 5, 7), 3, seed), up_case((2, 2, 9, 33), 2, seed)]
+    if kind == H.HF_MAXPOOL:
+        return [pool_case((2, 8, 24, 20), seed=seed), pool_case((1, 3, 9, 11), (2, 2), 2, 0, seed, offset=1),
+                pool_case((2, 2, 7, 13), (3, 2), 1, 1, seed, with_idx=False)]
     raise ValueError(kind)
 
 

@@ -84,8 +84,20 @@ def _up(n=1, c=2, h=5, w=5, s=2):
     return t
 
 
+def _pool(n=1, c=2, h=6, w=6, k=(3, 3, 2, 1), idx=True):
+    t = H.hf_task()
+    t.kind = H.HF_MAXPOOL
+    for i, v in enumerate(k):
+        t.p[i] = v
+    t.in_, t.out0 = _fake_ptr(), _fake_ptr(1 << 20)
+    t.out1 = _fake_ptr(1 << 21) if idx else None
+    t.n, t.c, t.h, t.w = n, c, h, w
+    return t
+
+
 def test_valid_tasks_pass():
-    for t in (_bn(), _mix(), _hist(), _im2col(), _up(), _mix(n=0), _hist(n=0), _im2col(n=0), _up(n=0)):
+    for t in (_bn(), _mix(), _hist(), _im2col(), _up(), _pool(), _pool(idx=False), _mix(n=0), _hist(n=0),
+              _im2col(n=0), _up(n=0), _pool(n=0)):
         assert H.hf_validate_task(t) == H.HF_OK
 
 
@@ -113,6 +125,25 @@ def test_bad_tasks_rejected(make, change):
 def test_bad_im2col_params(p):
     t = _im2col(h=4, w=4, k=p)
     assert H.hf_validate_task(t) == H.HF_EINVAL
+
+
+@pytest.mark.parametrize("p", [(0, 3, 1, 0), (3, 3, 0, 1), (3, 3, 1, -1), (3, 3, 1, 3), (2, 3, 1, 2),
+                               (65, 1, 1, 0), (3, 3, 65, 1)])
+def test_bad_maxpool_params(p):
+    # pad must stay below both window sizes, so that every window holds an element
+    assert H.hf_validate_task(_pool(k=p)) == H.HF_EINVAL
+
+
+def test_maxpool_shape_limits():
+    assert H.hf_validate_task(_pool(h=1, w=1, k=(3, 3, 1, 1))) == H.HF_OK  # one clipped window
+    assert H.hf_validate_task(_pool(h=1, w=1, k=(3, 3, 1, 0))) == H.HF_EINVAL  # no window fits
+    t = _pool()
+    t.out1 = _fake_ptr(2)  # misaligned index buffer
+    assert H.hf_validate_task(t) == H.HF_EINVAL
+    # stride 1 with padding has more outputs than inputs: both counts are bounded
+    assert H.hf_validate_task(_pool(n=1 << 16, c=1, h=181, w=181, k=(3, 3, 1, 1))) == H.HF_OK
+    assert H.hf_validate_task(_pool(n=1 << 16, c=1, h=181, w=181, k=(2, 2, 1, 1))) == H.HF_EINVAL
+    assert H.hf_scratch_bytes(_pool()) == 0
 
 
 def test_bad_hist_bins_and_upsample_scale():

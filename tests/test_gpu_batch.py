@@ -33,6 +33,9 @@ def check_instance(kind, x, outs):
         assert np.array_equal(outs[0].cpu().numpy(), oracle.im2col(xh, 3, 3, 1, 1))
     elif kind == H.HF_LDS_HIST:
         assert np.array_equal(outs[0].cpu().numpy().view(np.uint32).astype(np.uint64), oracle.hist256(xh))
+    elif kind == H.HF_MAXPOOL:
+        v, i = oracle.maxpool(xh, 3, 3, 2, 1)
+        assert np.array_equal(outs[0].cpu().numpy(), v) and np.array_equal(outs[1].cpu().numpy(), i)
     else:
         ref = oracle.upsample(xh, 2)
         mag = oracle.upsample_absmag(xh, 2)

@@ -68,3 +68,16 @@ def test_upsample_hist_full_size():
     ca2 = G.up_case((32, 64, 128, 128), 2, seed=3, check_slice=(slice(31, 32), slice(60, 64)))
     ca2.bufs = ca.bufs  # same seed, same bytes
     ca2.check(outs[:1])
+
+
+def test_maxpool_hist_full_size():
+    """The ResNet-stem pooling shape [64,64,112,112] 3x3/s2/p1 with indices,
+    fused with the 2^26-byte histogram: bit-exact vs back to back over every
+    element, first and last images against the oracle."""
+    ca = G.pool_case((64, 64, 112, 112), seed=4, check_images=[0, 63])
+    cb = G.hist_case(1 << 26, seed=2)
+    for cfg in [(8, 1024, 64), (12, 1024, 0), (2, 256, 80), (5, 512, 128)]:
+        print("maxpool[64,64,112,112] + lds_hist 2^26", cfg, flush=True)
+        outs = _fused_vs_serial(ca, cb, cfg)
+    ca.check(outs[:2])
+    cb.check(outs[2:])

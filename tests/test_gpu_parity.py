@@ -9,11 +9,12 @@ import pytest
 import torch
 
 from paper_2007_01277_amd import hfuse as H
+from paper_2007_01277_amd import inputs
 from tests import gpu_cases as G
 
 pytestmark = pytest.mark.gpu
 
-KINDS = range(5)
+KINDS = range(len(H.KIND_NAMES))
 BLOCKS = (256, 512, 1024)
 
 
@@ -160,6 +161,26 @@ def test_edge_cases():
     for ca, cb in itertools.combinations(cases[:8], 2):
         pr = H.make_pair(ca.task, cb.task)
         G.run_and_check(lambda: H.hf_run_fused(pr, 1, 2, 256), [ca, cb])
+
+
+def test_maxpool_ties_nan_and_clamped_windows():
+    """Ties keep the first element, NaN propagates, and windows clipped by the
+    padding match the oracle's scan -- solo and fused, with and without indices."""
+    x = inputs.normal_image((2, 3, 13, 10), seed=17)
+    x[0, 0] = np.round(x[0, 0])  # many ties
+    x[0, 1] = 1.0                # one constant plane: every window ties
+    x[1, 2, 4, 5] = np.nan
+    x[1, 2, 12, 9] = np.nan      # in the bottom-right window, reached by clamping
+    x[1, 0] = -np.inf
+    other = G.mix_case(4097, 3, seed=17)
+    for k, s, p in [((3, 3), 2, 1), ((2, 2), 1, 1), ((3, 2), 3, 0), ((5, 4), 2, 2)]:
+        for with_idx in (True, False):
+            c = G.pool_case(x.shape, k, s, p, x=x, with_idx=with_idx)
+            print(c.label, with_idx, flush=True)
+            for block in BLOCKS:
+                G.run_and_check(lambda: H.hf_run_solo(c.task, block), [c])
+            pr = H.make_pair(c.task, other.task)
+            G.run_and_check(lambda: H.hf_run_fused(pr, 3, 4, 256), [c, other])
 
 
 def test_bn_constant_input_exact():
