@@ -1,0 +1,136 @@
+"""Pins of the hash oracles (oracle/hashes.py) against what does not come from
+them: the worked examples and constants printed in FIPS 180-4 and RFC 7693,
+the published FNV-1 test values, an independent implementation (hashlib), and
+closed forms and dependence checks of the Ethash-like loop."""
+import hashlib
+import os
+
+import numpy as np
+import pytest
+
+from oracle import hashes as O
+from paper_2007_01277_amd import inputs
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rows(name):
+    with open(os.path.join(GOLD, name)) as fh:
+        return [ln.split() for ln in fh if ln.strip() and not ln.startswith("#")]
+
+
+def test_sha256_published_example():
+    for msg, dig in _rows("sha256_fips180_4_abc.txt"):
+        assert O.sha256(msg.encode()).hex() == dig
+
+
+def test_sha256_constants_published_values():
+    K, H0 = O.sha256_constants()
+    for name, i, v in _rows("sha256_fips180_4_constants.txt"):
+        assert (K if name == "K" else H0)[int(i)] == int(v, 16), (name, i)
+    assert len(set(K)) == 64 and len(H0) == 8
+
+
+@pytest.mark.parametrize("length", [0, 1, 3, 55, 56, 63, 64, 65, 80, 119, 120, 128, 191, 300])
+def test_sha256_matches_hashlib_at_padding_boundaries(length):
+    msg = bytes(inputs.rng(length).integers(0, 256, size=length, dtype=np.uint8))
+    assert O.sha256(msg) == hashlib.sha256(msg).digest()
+
+
+def test_sha256d_of_headers_matches_hashlib():
+    hdr = bytes(inputs.rng(5).integers(0, 256, size=80, dtype=np.uint8))
+    idx = [0, 1, 2, 1000, 65535]
+    got = O.sha256d(hdr, 0xFFFFFFF0, idx)
+    for i, d in zip(idx, got):
+        m = hdr[:76] + ((0xFFFFFFF0 + i) & 0xFFFFFFFF).to_bytes(4, "little")  # wraps past 2^32
+        assert d == hashlib.sha256(hashlib.sha256(m).digest()).digest()
+
+
+def test_blake2b_published_example():
+    for msg, n, dig in _rows("blake2b_rfc7693_abc.txt"):
+        assert O.blake2b(msg.encode(), int(n)).hex() == dig
+
+
+def test_blake2b_iv_is_the_sha512_initial_value():
+    # RFC 7693 2.6: IV[0] = 0x6A09E667F3BCC908, whose high half is SHA-256's H0[0]
+    iv = O.blake2b_iv()
+    _, H0 = O.sha256_constants()
+    assert [v >> 32 for v in iv] == H0
+    assert iv[0] == 0x6A09E667F3BCC908
+
+
+@pytest.mark.parametrize("length", [0, 1, 80, 127, 128, 129, 256, 300])
+@pytest.mark.parametrize("outlen", [32, 64, 20])
+def test_blake2b_matches_hashlib(length, outlen):
+    msg = bytes(inputs.rng(length + outlen).integers(0, 256, size=length, dtype=np.uint8))
+    assert O.blake2b(msg, outlen) == hashlib.blake2b(msg, digest_size=outlen).digest()
+
+
+def test_blake2b_sigma_rows_are_permutations():
+    for row in O.SIGMA:
+        assert sorted(row) == list(range(16))
+
+
+def test_blake2b_of_headers_matches_hashlib():
+    hdr = bytes(inputs.rng(6).integers(0, 256, size=80, dtype=np.uint8))
+    idx = [0, 7, 123456]
+    for i, d in zip(idx, O.blake2b_header(hdr, 17, idx)):
+        assert d == hashlib.blake2b(hdr[:76] + (17 + i).to_bytes(4, "little"), digest_size=32).digest()
+
+
+def test_fnv1_published_values():
+    for msg, v in _rows("fnv1_32_test_values.txt"):
+        assert O.fnv1_32(b"" if msg == "-" else msg.encode()) == int(v, 16)
+
+
+def _table(R, seed):
+    return inputs.rng(seed).integers(0, 2 ** 32, size=(R, 32), dtype=np.uint64).astype(np.uint32)
+
+
+def test_ethash_like_zero_table_closed_form():
+    # with an all-zero table every access multiplies each mix word by the FNV
+    # prime, whatever rows are read: mix_j = s_j * P^64, then the 4-to-1 fold
+    hdr = bytes(inputs.rng(8).integers(0, 256, size=80, dtype=np.uint8))
+    nonce = 99
+    words = [int.from_bytes(hdr[4 * k:4 * k + 4], "little") for k in range(19)] + [nonce]
+    h = 2166136261
+    for w in words:
+        h = ((h * 16777619) % 2 ** 32) ^ w
+    s = [h]
+    for k in range(1, 16):
+        s.append(((s[-1] * 16777619) % 2 ** 32) ^ k)
+    p64 = pow(16777619, 64, 2 ** 32)
+    mix = [(s[j % 16] * p64) % 2 ** 32 for j in range(32)]
+    out = []
+    for k in range(8):
+        a = mix[4 * k]
+        for t in range(1, 4):
+            a = ((a * 16777619) % 2 ** 32) ^ mix[4 * k + t]
+        out.append(a)
+    want = b"".join(v.to_bytes(4, "little") for v in out)
+    assert O.ethash_like_one(hdr, nonce, np.zeros((37, 32), np.uint32)) == want
+
+
+def test_ethash_like_depends_exactly_on_the_rows_it_reads():
+    # flipping a word of a row changes the digest iff the row is read
+    hdr = bytes(inputs.rng(9).integers(0, 256, size=80, dtype=np.uint8))
+    R = 96
+    T = _table(R, 10)
+    seen = []
+    base = O.ethash_like_one(hdr, 5, T, seen)
+    assert len(seen) == 64 and all(0 <= p < R for p in seen)
+    for r in range(R):
+        T2 = T.copy()
+        T2[r, 3] ^= 0x10000
+        assert (O.ethash_like_one(hdr, 5, T2) != base) == (r in seen), r
+
+
+def test_ethash_like_rows_spread_over_the_table():
+    # 64 accesses x 200 nonces over 1024 rows: the accessed rows cover the table
+    hdr = bytes(range(80))
+    T = _table(1024, 11)
+    rows = []
+    for n in range(200):
+        O.ethash_like_one(hdr, n, T, rows)
+    counts = np.bincount(rows, minlength=1024)
+    assert counts.min() > 0 and counts.max() < 40
