@@ -6,7 +6,8 @@ integer mixing over 2^24 uint32 seeds.  ``--workload`` selects one of the
 memory + atomic pairs instead: im2col [32,128,56,56] 3x3/s1/p1, bilinear x2
 upsample [32,64,128,128] or 3x3/s2/p1 max pooling with indices over the
 ResNet-stem activations [64,64,112,112], each with a 256-bin histogram of 2^26
-Zipf bytes.
+Zipf bytes; or the crypto pair: 327,680 Ethash-like hashes (64 random 128-byte
+rows each of a 1 GiB table) with 2^22 SHA-256d hashes of 80-byte headers.
 
 A step is one fused launch of the pair at the configuration the exhaustive
 tuner picks (split, workgroup size, VGPR bound); the same inputs are also run
@@ -34,7 +35,8 @@ METRIC = "fused vs back-to-back time speedup (%) per pair at 1 MI355X; HBM GB/s 
 INT_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
 OPS_PER_ROUND = 8  # 3 shifts, 3 xors, 1 multiply, 1 add
-WORKLOADS = ("bn_stats+int_mix", "im2col+lds_hist", "upsample+lds_hist", "maxpool+lds_hist")
+WORKLOADS = ("bn_stats+int_mix", "im2col+lds_hist", "upsample+lds_hist", "maxpool+lds_hist", "ethash+sha256d")
+ETH_ROWS = 1 << 23  # a 1 GiB table, four times the last-level cache
 
 
 def parse():
@@ -109,6 +111,24 @@ class Workload:
             self.desc = f"bn_stats fp32 {list(self.shape)} + int_mix u32 2^24 x {self.rounds} rounds"
             self.bound = "alu"
             self.kernel = "fused_cap/fused_nocap<BnStats,IntMix>"
+        elif name == "ethash+sha256d":
+            self.n_eth, self.n_sha = 5 << 16, 1 << 22
+            self.hdr = inputs.header80(21)
+            self.nonce = inputs.nonce0(21)
+            hd = torch.from_numpy(self.hdr.view(np.int32)).cuda()
+            self.table = inputs.cuda_eth_table(ETH_ROWS, 22)
+            oe = torch.empty((self.n_eth, 8), dtype=torch.int32, device="cuda")
+            osha = torch.empty((self.n_sha, 8), dtype=torch.int32, device="cuda")
+            self.ta = H.task_ethash(hd, self.table, oe, self.nonce, self.n_eth)
+            self.tb = H.task_sha256d(hd, osha, self.nonce, self.n_sha)
+            self.outs = [oe, osha]
+            self.bufs = [hd, self.table]
+            self.alg_bytes = self.n_eth * (64 * 128 + 32) + self.n_sha * 32
+            self.alg_ops = 0
+            self.desc = ("ethash-like 327680 hashes over a 1 GiB table + sha256d 2^22 hashes of an 80-byte "
+                         "header")
+            self.bound = "hbm"
+            self.kernel = "fused_cap/fused_nocap<Sha256d,EthashLike>"
         else:
             self.hist = inputs.zipf_u8(1 << 26, seed=2)
             hd = torch.from_numpy(self.hist).cuda()
@@ -151,9 +171,26 @@ class Workload:
         torch.cuda.synchronize()
 
     def cpu_baseline(self):
-        """The CPU oracle (plain C, double accumulation, one thread) on the same step."""
+        """The CPU oracle (plain C, double accumulation, one thread) on the same step;
+        for the hash pair the Python oracle on a bounded sample, scaled."""
+        import numpy as np
+
         import oracle
         t0 = time.perf_counter()
+        if self.name == "ethash+sha256d":
+            from oracle import hashes as OH
+            tab = self.table.cpu().numpy().view(np.uint32)
+            t0 = time.perf_counter()
+            ke, ks = 2000, 4000  # a bounded sample of each kernel's instances, scaled below
+            for i in range(ke):
+                OH.ethash_like_one(self.hdr.tobytes(), self.nonce + i, tab)
+            t1 = time.perf_counter()
+            OH.sha256d(self.hdr.tobytes(), self.nonce, range(ks))
+            t2 = time.perf_counter()
+            full = (t1 - t0) * self.n_eth / ke + (t2 - t1) * self.n_sha / ks
+            return {"value": round(full * 1e3, 1), "unit": "ms/step", "cores": 1, "kind": "oracle",
+                    "sample": f"{ke} Ethash-like and {ks} SHA-256d hashes ({(t2 - t0):.1f} s, single thread), "
+                              f"scaled to the step's {self.n_eth} + {self.n_sha} hashes"}
         if self.name == "bn_stats+int_mix":
             oracle.bn_stats(self.x)
             t1 = time.perf_counter()
@@ -273,7 +310,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+u32" if w.name == "bn_stats+int_mix" else "f32+u8",
+        "dtype": {"bn_stats+int_mix": "f32+u32", "ethash+sha256d": "u32"}.get(w.name, "f32+u8"),
         "data": "synthetic",
         "config": {
             "workload": w.desc,

@@ -64,7 +64,10 @@ typedef enum {
   HF_LDS_HIST = 3,  /* 256-bin histogram of uint8 values (bin = byte value)          */
   HF_UPSAMPLE = 4,  /* bilinear upsampling by an integer factor, half-pixel centres  */
   HF_MAXPOOL = 5,   /* 2-D max pooling with the winner's flat index (Sec. IV-A)      */
-  HF_NUM_KINDS = 6
+  HF_SHA256D = 6,   /* SHA-256(SHA-256(header with nonce)), FIPS 180-4               */
+  HF_BLAKE2B = 7,   /* BLAKE2b, 32-byte digest, no key, of header with nonce, RFC 7693 */
+  HF_ETHASH = 8,    /* Ethash-like: 64 FNV folds of random 128-byte table rows        */
+  HF_NUM_KINDS = 9
 } hf_kind;
 
 /* One kernel instance.
@@ -74,6 +77,8 @@ typedef enum {
  *                  MAXPOOL                    : float  [n][c][h][w], contiguous
  *                  INT_MIX                    : uint32 [n]
  *                  LDS_HIST                   : uint8  [n]
+ *                  SHA256D, BLAKE2B, ETHASH   : the 80-byte block header; instance
+ *                      i hashes header[0:76] || le32(p[0] + i mod 2^32)
  *   out0         device output
  *                  BN_STATS : float mean[c]
  *                  INT_MIX  : uint32 [n]
@@ -82,6 +87,8 @@ typedef enum {
  *                  UPSAMPLE : float [n][c][h*s][w*s]
  *                  MAXPOOL  : float [n][c][Ho][Wo], Ho=(h+2*pad-kh)/stride+1 (same for Wo):
  *                             the maximum over the window's in-range elements
+ *                  SHA256D, BLAKE2B, ETHASH : uint8 [n][32] digests, 16-byte aligned
+ *                             (ETHASH: the eight folded mix words, little-endian)
  *   out1         BN_STATS: float var[c] (biased, divided by n*h*w)
  *                MAXPOOL : int32 [n][c][Ho][Wo] flat index y*w + x, within its
  *                          input plane, of the element each maximum came from
@@ -97,6 +104,11 @@ typedef enum {
  *                UPSAMPLE: p[0] = integer scale s in [1, 16]
  *                MAXPOOL : p[0]=kh, p[1]=kw, p[2]=stride, p[3]=pad with
  *                          0 <= pad < min(kh, kw) (padded positions never win)
+ *                SHA256D, BLAKE2B, ETHASH: p[0] = first nonce (as uint32)
+ *   in1          ETHASH: the table, uint32 [h][32] (h rows of 128 bytes,
+ *                16-byte aligned, 1 <= h < 2^32); unused (NULL) otherwise.
+ *                The row of access j of a hash is fnv(j ^ s0, mix[j % 32]) % h
+ *                with fnv(a, b) = (a * 16777619) ^ b mod 2^32.
  * Input and output buffers must be 4-byte aligned (LDS_HIST input: any) and must
  * not overlap.  Element counts must stay below 2^31 per buffer. */
 typedef struct {
@@ -108,6 +120,7 @@ typedef struct {
   void* out1;
   void* scratch;
   int64_t n, c, h, w;
+  const void* in1;
 } hf_task;
 
 /* Two independent kernel instances to be fused (K1 and K2 of the Generate
@@ -259,7 +272,7 @@ int hf_register_bound(int d1, int d2, int vgpr_a, int vgpr_b, int lds_fused);
  * used.  Trained and evaluated on the GPU by the library's own kernels.  One
  * model per process, on the device current at hf_mlp_init.  Unless stated
  * otherwise, arrays are HOST pointers, row-major. */
-#define HF_MLP_FEATURES 34 /* 2 * (HF_NUM_KINDS + 7) + 8; the last is log2(sum of solo times) */
+#define HF_MLP_FEATURES 40 /* 2 * (HF_NUM_KINDS + 7) + 8; the last is log2(sum of solo times) */
 /* Allocates the model for d_in features: He-uniform weights from `seed`
  * (splitmix64), zero biases, identity feature standardisation. */
 int hf_mlp_init(int d_in, uint64_t seed);

@@ -30,9 +30,12 @@ from . import hfuse as H
 from . import inputs
 
 
-def draw(count: int = 1000, seed: int = 3, kmin: int = 12, kmax: int = 18):
+DATA_KINDS = (H.HF_BN_STATS, H.HF_INT_MIX, H.HF_IM2COL, H.HF_LDS_HIST, H.HF_UPSAMPLE, H.HF_MAXPOOL)
+
+
+def draw(count: int = 1000, seed: int = 3, kmin: int = 12, kmax: int = 18, kinds=DATA_KINDS):
     g = inputs.rng(seed)
-    kinds = g.integers(0, len(H.KIND_NAMES), size=count)
+    kinds = np.asarray(kinds)[g.integers(0, len(kinds), size=count)]
     logs = g.integers(kmin, kmax + 1, size=count)
     groups, gid, i = [], 0, 0
     while i < count:
@@ -51,6 +54,7 @@ class Workload:
         import torch
         self.kinds, self.logs = kinds, logs
         self.tasks, self.bufs, self.outs, self.ins = [], [], [], []
+        self.meta = []  # per instance: (nonce0, table tensor) of hash kinds, else None
         for i, (kind, k) in enumerate(zip(kinds, logs)):
             n = 1 << k
             s = seed * 100000 + i
@@ -73,10 +77,24 @@ class Workload:
                 x = inputs.cuda_uint32(n, s)
                 o = [torch.empty_like(x)]
                 t = H.task_int_mix(x, o[0], 32)
+            elif kind in (H.HF_SHA256D, H.HF_BLAKE2B, H.HF_ETHASH):
+                m = max(1, n >> 6)  # a hash counts as 64 elements of work
+                x = torch.from_numpy(inputs.header80(s).view(np.int32)).cuda()
+                o = [torch.empty((m, 8), dtype=torch.int32, device="cuda")]
+                tab = None
+                if kind == H.HF_ETHASH:
+                    tab = inputs.cuda_eth_table(4099, s)
+                    self.bufs.append(tab)
+                    t = H.task_ethash(x, tab, o[0], inputs.nonce0(s), m)
+                else:
+                    t = (H.task_sha256d if kind == H.HF_SHA256D else H.task_blake2b)(x, o[0], inputs.nonce0(s), m)
+                self.meta.append((inputs.nonce0(s), tab))
             else:
                 x = inputs.cuda_zipf_u8(n, s)
                 o = [torch.empty(256, dtype=torch.int32, device="cuda")]
                 t = H.task_lds_hist(x, o[0])
+            if len(self.meta) < len(self.tasks) + 1:
+                self.meta.append(None)
             nb = H.hf_scratch_bytes(t)
             if nb > 0:
                 scr = torch.zeros(nb // 4 + 64, dtype=torch.int32, device="cuda")

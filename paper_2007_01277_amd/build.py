@@ -25,7 +25,7 @@ FLAGS = [
     "-Wno-unused-command-line-argument",
 ]
 
-NUM_KINDS = 6
+NUM_KINDS = 9
 PAIRS = [(a, b) for a in range(NUM_KINDS) for b in range(a, NUM_KINDS)]
 
 

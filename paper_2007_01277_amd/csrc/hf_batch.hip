@@ -41,7 +41,10 @@ struct BatchTables {
   uint32_t total_items;
 };
 
-template <class Bar>
+// HASH: the variant that also runs the hash kinds.  The hash bodies need more
+// registers than the others, so batches without them use the variant that
+// leaves them out and keeps five waves per SIMD without spilling.
+template <bool HASH, class Bar>
 __device__ __forceinline__ void run_body(int kind, const DevTask& t, const Part& p, Bar& bar, uint32_t* lds) {
   switch (kind) {
     case HF_BN_STATS: BnStats::run(t, p, bar, lds); break;
@@ -50,16 +53,27 @@ __device__ __forceinline__ void run_body(int kind, const DevTask& t, const Part&
     case HF_LDS_HIST: LdsHist::run(t, p, bar, lds); break;
     case HF_UPSAMPLE: Upsample::run(t, p, bar, lds); break;
     case HF_MAXPOOL: Maxpool::run(t, p, bar, lds); break;
-    default: break;
+    default:
+      if constexpr (HASH) {
+        switch (kind) {
+          case HF_SHA256D: Sha256d::run(t, p, bar, lds); break;
+          case HF_BLAKE2B: Blake2b::run(t, p, bar, lds); break;
+          case HF_ETHASH: EthashLike::run(t, p, bar, lds); break;
+          default: break;
+        }
+      }
+      break;
   }
 }
+
+constexpr bool is_hash_kind(int kind) { return kind == HF_SHA256D || kind == HF_BLAKE2B || kind == HF_ETHASH; }
 
 // LDS: kMaxMembers interval-barrier counters, then (dynamic) one histogram
 // region per histogram member of the largest group's histogram count.
 extern __shared__ uint32_t hf_batch_hist_lds[];
 
-template <int BLOCK>
-__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5))) k_batch(BatchTables T) {
+template <int BLOCK, bool HASH, int WPE>
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) k_batch(BatchTables T) {
   __shared__ uint32_t smem[kMaxMembers];
   __shared__ uint32_t item_sh[2];
   const uint32_t wave = uniform(threadIdx.x >> 6);
@@ -106,7 +120,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5)))
       for (int i = 0; i < (int)(sizeof(DevTask) / 4); ++i) dst[i] = uniform(src[i]);
       const int32_t slot = (int32_t)uniform((uint32_t)T.lds_slot[mine]);
       uint32_t* lds = slot >= 0 ? hf_batch_hist_lds + (uint32_t)slot * LdsHist::lds_words(BLOCK) : nullptr;
-      run_body((int)uniform((uint32_t)T.kinds[mine]), dt, p, bar, lds);
+      run_body<HASH>((int)uniform((uint32_t)T.kinds[mine]), dt, p, bar, lds);
     }
     __syncthreads();  // item boundary: every interval has finished
   }
@@ -115,6 +129,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(5)))
 // ------------------------------------------------------------------ host side
 struct Batch {
   int device = 0, block = 256, ntask = 0, ngroup = 0;
+  bool hash = false;  // some task is a hash kind: the hash-capable kernel variant
   uint32_t total_items = 0;
   std::vector<hf_task> tasks;
   void* dmem = nullptr;     // tables + queue
@@ -127,11 +142,14 @@ struct Batch {
   size_t lds_bytes = 0;  // dynamic LDS per workgroup
 };
 
-static const void* batch_kernel(int block) {
+static const void* batch_kernel(int block, bool hash) {
   switch (block) {
-    case 256: return reinterpret_cast<const void*>(&k_batch<256>);
-    case 512: return reinterpret_cast<const void*>(&k_batch<512>);
-    case 1024: return reinterpret_cast<const void*>(&k_batch<1024>);
+    case 256: return hash ? reinterpret_cast<const void*>(&k_batch<256, true, 4>)
+                          : reinterpret_cast<const void*>(&k_batch<256, false, 5>);
+    case 512: return hash ? reinterpret_cast<const void*>(&k_batch<512, true, 4>)
+                          : reinterpret_cast<const void*>(&k_batch<512, false, 5>);
+    case 1024: return hash ? reinterpret_cast<const void*>(&k_batch<1024, true, 4>)
+                           : reinterpret_cast<const void*>(&k_batch<1024, false, 5>);
   }
   return nullptr;
 }
@@ -162,6 +180,9 @@ static double est_cost_us(const hf_task* t) {
       ops = 4 * kh * kw * out;
       break;
     }
+    case HF_SHA256D: bytes = 32 * n; ops = 3 * 64 * 24.0 * n; break;  // 3 compressions of ~24 ops/round
+    case HF_BLAKE2B: bytes = 32 * n; ops = 12 * 8 * 28.0 * n; break;  // 12 rounds of 8 G of ~28 ops
+    case HF_ETHASH: bytes = (64 * 128.0 + 32) * n; ops = 64 * 40.0 * n / 8; break;  // latency-bound rows
   }
   return std::max(bytes / 5.0e6, ops / 38.0e6);  // us at ~5 TB/s and ~38 T lane-op/s
 }
@@ -206,7 +227,7 @@ static int batch_free(Batch* B) {
 static int batch_launch(Batch* B, hipStream_t st) {
   void* args[] = {&B->tab};
   hipError_t e =
-      hipLaunchKernel(batch_kernel(B->block), dim3(B->grid), dim3(B->block), args, B->lds_bytes, st);
+      hipLaunchKernel(batch_kernel(B->block, B->hash), dim3(B->grid), dim3(B->block), args, B->lds_bytes, st);
   return e == hipSuccess ? HF_OK : record_hip(e);
 }
 
@@ -301,6 +322,7 @@ static int batch_create(const hf_task* tasks, int ntask, const int32_t* group_of
         return rc;
       }
       kinds[i] = tasks[i].kind;
+      B->hash = B->hash || is_hash_kind(tasks[i].kind);
       need = std::max(need, useful_wgs(&tasks[i], dts[i], waves[i]));
       bytes += est_cost_us(&tasks[i]) * 5.0e6;
     }
@@ -350,7 +372,7 @@ static int batch_create(const hf_task* tasks, int ntask, const int32_t* group_of
   B->tab.total_items = B->total_items;
   B->lds_bytes = (size_t)max_hist * LdsHist::lds_words(block) * 4u;
   int occ = 0;
-  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, batch_kernel(block), block, B->lds_bytes)) !=
+  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, batch_kernel(block, B->hash), block, B->lds_bytes)) !=
       hipSuccess) {
     batch_free(B);
     return record_hip(e);

@@ -83,6 +83,19 @@ struct PoolArgs {  // max pooling with the winner's flat index
   FastDiv div_plane, div_wo;  // by Ho*Wo and by Wo
 };
 
+struct ShaArgs {  // SHA-256d and BLAKE2b over header || nonce
+  const uint32_t* hdr;  // 20 words: the 80-byte header
+  uint32_t* out;        // [n][8] words: 32-byte digests
+  uint32_t nonce0, n;
+};
+
+struct EthArgs {  // Ethash-like folds of table rows
+  const uint32_t* hdr;  // 20 words: the 80-byte header
+  const uint4* table;   // [rows][8] uint4: rows of 128 bytes
+  uint32_t* out;        // [n][8] words
+  uint32_t nonce0, n, rows;
+};
+
 union DevTask {
   BnArgs bn;
   MixArgs mix;
@@ -90,6 +103,8 @@ union DevTask {
   Im2colArgs im2col;
   UpArgs up;
   PoolArgs pool;
+  ShaArgs sha;
+  EthArgs eth;
 };
 
 // Agent-scope helpers for partial results exchanged between workgroups.
@@ -679,3 +694,5 @@ struct Maxpool {
 };
 
 }  // namespace hf
+
+#include "hf_hash.hpp"

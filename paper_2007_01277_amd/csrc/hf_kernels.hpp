@@ -24,6 +24,9 @@ template <> struct BodyOf<2> { using T = Im2col; };
 template <> struct BodyOf<3> { using T = LdsHist; };
 template <> struct BodyOf<4> { using T = Upsample; };
 template <> struct BodyOf<5> { using T = Maxpool; };
+template <> struct BodyOf<6> { using T = Sha256d; };
+template <> struct BodyOf<7> { using T = Blake2b; };
+template <> struct BodyOf<8> { using T = EthashLike; };
 
 constexpr uint32_t max1(uint32_t v) { return v ? v : 1u; }
 

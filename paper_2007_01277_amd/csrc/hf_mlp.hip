@@ -311,6 +311,18 @@ static void alg_work(const hf_task* t, double* bytes, double* ops) {
       *ops = 4.0 * kh * kw * out;
       break;
     }
+    case HF_SHA256D:
+      *bytes = 32.0 * n;
+      *ops = 3.0 * 64 * 24 * n;
+      break;
+    case HF_BLAKE2B:
+      *bytes = 32.0 * n;
+      *ops = 12.0 * 8 * 28 * n;
+      break;
+    case HF_ETHASH:
+      *bytes = (64.0 * 128 + 32) * n;
+      *ops = 64.0 * 40 * n / 8;
+      break;
   }
 }
 

@@ -1,6 +1,6 @@
 // hf_pairs.hip -- fused instantiations of one ordered pair of kernel kinds.
 // Compiled once per pair with -DHF_KA=<kind> -DHF_KB=<kind> (HF_KA <= HF_KB), so
-// the twenty-one pairs build in parallel; each object exports hf_table_<KA>_<KB>.
+// the forty-five pairs build in parallel; each object exports hf_table_<KA>_<KB>.
 #include "hf_kernels.hpp"
 
 #if !defined(HF_KA) || !defined(HF_KB)

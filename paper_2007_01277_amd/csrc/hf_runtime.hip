@@ -25,11 +25,17 @@ int record_hip(hipError_t e) {
 // ------------------------------------------------------------------ registry
 #define HF_DECLARE_TABLE(KA, KB) const KernelEntry* hf_table_##KA##_##KB(int* count);
 HF_DECLARE_TABLE(0, 0) HF_DECLARE_TABLE(0, 1) HF_DECLARE_TABLE(0, 2) HF_DECLARE_TABLE(0, 3)
-HF_DECLARE_TABLE(0, 4) HF_DECLARE_TABLE(0, 5) HF_DECLARE_TABLE(1, 1) HF_DECLARE_TABLE(1, 2)
-HF_DECLARE_TABLE(1, 3) HF_DECLARE_TABLE(1, 4) HF_DECLARE_TABLE(1, 5) HF_DECLARE_TABLE(2, 2)
-HF_DECLARE_TABLE(2, 3) HF_DECLARE_TABLE(2, 4) HF_DECLARE_TABLE(2, 5) HF_DECLARE_TABLE(3, 3)
-HF_DECLARE_TABLE(3, 4) HF_DECLARE_TABLE(3, 5) HF_DECLARE_TABLE(4, 4) HF_DECLARE_TABLE(4, 5)
-HF_DECLARE_TABLE(5, 5)
+HF_DECLARE_TABLE(0, 4) HF_DECLARE_TABLE(0, 5) HF_DECLARE_TABLE(0, 6) HF_DECLARE_TABLE(0, 7)
+HF_DECLARE_TABLE(0, 8) HF_DECLARE_TABLE(1, 1) HF_DECLARE_TABLE(1, 2) HF_DECLARE_TABLE(1, 3)
+HF_DECLARE_TABLE(1, 4) HF_DECLARE_TABLE(1, 5) HF_DECLARE_TABLE(1, 6) HF_DECLARE_TABLE(1, 7)
+HF_DECLARE_TABLE(1, 8) HF_DECLARE_TABLE(2, 2) HF_DECLARE_TABLE(2, 3) HF_DECLARE_TABLE(2, 4)
+HF_DECLARE_TABLE(2, 5) HF_DECLARE_TABLE(2, 6) HF_DECLARE_TABLE(2, 7) HF_DECLARE_TABLE(2, 8)
+HF_DECLARE_TABLE(3, 3) HF_DECLARE_TABLE(3, 4) HF_DECLARE_TABLE(3, 5) HF_DECLARE_TABLE(3, 6)
+HF_DECLARE_TABLE(3, 7) HF_DECLARE_TABLE(3, 8) HF_DECLARE_TABLE(4, 4) HF_DECLARE_TABLE(4, 5)
+HF_DECLARE_TABLE(4, 6) HF_DECLARE_TABLE(4, 7) HF_DECLARE_TABLE(4, 8) HF_DECLARE_TABLE(5, 5)
+HF_DECLARE_TABLE(5, 6) HF_DECLARE_TABLE(5, 7) HF_DECLARE_TABLE(5, 8) HF_DECLARE_TABLE(6, 6)
+HF_DECLARE_TABLE(6, 7) HF_DECLARE_TABLE(6, 8) HF_DECLARE_TABLE(7, 7) HF_DECLARE_TABLE(7, 8)
+HF_DECLARE_TABLE(8, 8)
 const KernelEntry* hf_table_solo(int* count);
 
 static std::vector<KernelEntry>& registry() {
@@ -37,10 +43,13 @@ static std::vector<KernelEntry>& registry() {
   static std::once_flag once;
   std::call_once(once, [] {
     const KernelEntry* (*tabs[])(int*) = {
-        hf_table_0_0, hf_table_0_1, hf_table_0_2, hf_table_0_3, hf_table_0_4, hf_table_0_5,
-        hf_table_1_1, hf_table_1_2, hf_table_1_3, hf_table_1_4, hf_table_1_5, hf_table_2_2,
-        hf_table_2_3, hf_table_2_4, hf_table_2_5, hf_table_3_3, hf_table_3_4, hf_table_3_5,
-        hf_table_4_4, hf_table_4_5, hf_table_5_5, hf_table_solo};
+        hf_table_0_0, hf_table_0_1, hf_table_0_2, hf_table_0_3, hf_table_0_4, hf_table_0_5, hf_table_0_6,
+        hf_table_0_7, hf_table_0_8, hf_table_1_1, hf_table_1_2, hf_table_1_3, hf_table_1_4, hf_table_1_5,
+        hf_table_1_6, hf_table_1_7, hf_table_1_8, hf_table_2_2, hf_table_2_3, hf_table_2_4, hf_table_2_5,
+        hf_table_2_6, hf_table_2_7, hf_table_2_8, hf_table_3_3, hf_table_3_4, hf_table_3_5, hf_table_3_6,
+        hf_table_3_7, hf_table_3_8, hf_table_4_4, hf_table_4_5, hf_table_4_6, hf_table_4_7, hf_table_4_8,
+        hf_table_5_5, hf_table_5_6, hf_table_5_7, hf_table_5_8, hf_table_6_6, hf_table_6_7, hf_table_6_8,
+        hf_table_7_7, hf_table_7_8, hf_table_8_8, hf_table_solo};
     for (auto f : tabs) {
       int n = 0;
       const KernelEntry* e = f(&n);
@@ -217,6 +226,20 @@ int validate_task(const hf_task* t) {
       if (!aligned(t->in, 4) || !aligned(t->out0, 4) || !aligned(t->out1, 4)) return HF_EINVAL;
       return HF_OK;
     }
+    case HF_SHA256D:
+    case HF_BLAKE2B:
+    case HF_ETHASH: {
+      if (t->n > kMaxElems / 8) return HF_EINVAL;  // 8 digest words per instance
+      if (t->n > 0) {
+        if (!t->in || !t->out0) return HF_EINVAL;
+        if (!aligned(t->in, 4) || !aligned(t->out0, 16)) return HF_EINVAL;
+      }
+      if (t->kind == HF_ETHASH) {
+        if (t->h < 1 || t->h > (int64_t)UINT32_MAX) return HF_EINVAL;  // table rows
+        if (t->n > 0 && (!t->in1 || !aligned(t->in1, 16))) return HF_EINVAL;
+      }
+      return HF_OK;
+    }
   }
   return HF_EINVAL;
 }
@@ -348,6 +371,25 @@ int prepare(const hf_task* t, void* scratch, DevTask* dt) {
       a.div_wo = make_fastdiv(a.Wo);
       return HF_OK;
     }
+    case HF_SHA256D:
+    case HF_BLAKE2B: {
+      ShaArgs& a = dt->sha;
+      a.hdr = static_cast<const uint32_t*>(t->in);
+      a.out = static_cast<uint32_t*>(t->out0);
+      a.nonce0 = (uint32_t)t->p[0];
+      a.n = (uint32_t)t->n;
+      return HF_OK;
+    }
+    case HF_ETHASH: {
+      EthArgs& a = dt->eth;
+      a.hdr = static_cast<const uint32_t*>(t->in);
+      a.table = static_cast<const uint4*>(t->in1);
+      a.out = static_cast<uint32_t*>(t->out0);
+      a.nonce0 = (uint32_t)t->p[0];
+      a.n = (uint32_t)t->n;
+      a.rows = (uint32_t)t->h;
+      return HF_OK;
+    }
   }
   return HF_EINVAL;
 }
@@ -364,6 +406,9 @@ int64_t useful_wgs(const hf_task* t, const DevTask& d, int waves) {
     case HF_IM2COL: units = cdiv(d.im2col.units, waves); break;
     case HF_UPSAMPLE: units = cdiv(d.up.units, waves); break;
     case HF_MAXPOOL: units = cdiv(d.pool.units, waves); break;
+    case HF_SHA256D:
+    case HF_BLAKE2B: units = cdiv(d.sha.n, 64 * waves); break;
+    case HF_ETHASH: units = cdiv(d.eth.n, EthashLike::kPerWave * waves); break;
   }
   return std::max<int64_t>(units, 1);
 }

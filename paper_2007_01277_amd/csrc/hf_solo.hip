@@ -8,7 +8,8 @@ namespace hf {
 
 const KernelEntry* hf_table_solo(int* count) {
   static const KernelEntry tab[] = {HF_SOLO_KIND(0) HF_SOLO_KIND(1) HF_SOLO_KIND(2) HF_SOLO_KIND(3)
-                                        HF_SOLO_KIND(4) HF_SOLO_KIND(5)};
+                                        HF_SOLO_KIND(4) HF_SOLO_KIND(5) HF_SOLO_KIND(6)
+                                            HF_SOLO_KIND(7) HF_SOLO_KIND(8)};
   *count = (int)(sizeof(tab) / sizeof(tab[0]));
   return tab;
 }

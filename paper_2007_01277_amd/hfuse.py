@@ -14,8 +14,9 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("HFUSE_LIB") or os.path.join(PKG, "libhfuse.so")
 
 HF_OK, HF_EINVAL, HF_EUNSUPPORTED, HF_EHIP, HF_ETIMEOUT, HF_ENOMEM, HF_ENOMODEL = 0, -1, -2, -3, -4, -5, -6
-HF_BN_STATS, HF_INT_MIX, HF_IM2COL, HF_LDS_HIST, HF_UPSAMPLE, HF_MAXPOOL = range(6)
-KIND_NAMES = ["bn_stats", "int_mix", "im2col", "lds_hist", "upsample", "maxpool"]
+(HF_BN_STATS, HF_INT_MIX, HF_IM2COL, HF_LDS_HIST, HF_UPSAMPLE, HF_MAXPOOL, HF_SHA256D, HF_BLAKE2B,
+ HF_ETHASH) = range(9)
+KIND_NAMES = ["bn_stats", "int_mix", "im2col", "lds_hist", "upsample", "maxpool", "sha256d", "blake2b", "ethash"]
 HF_SERIAL, HF_STREAMS = 0, 1
 HF_TUNE_EXHAUSTIVE, HF_TUNE_PAPER, HF_TUNE_NAIVE, HF_TUNE_MLP = range(4)
 CAPS = (0, 64, 80, 96, 128)
@@ -31,7 +32,8 @@ class hf_task(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("p", ctypes.c_int32 * 4), ("reserved", ctypes.c_int32),
                 ("in_", ctypes.c_void_p), ("out0", ctypes.c_void_p), ("out1", ctypes.c_void_p),
                 ("scratch", ctypes.c_void_p),
-                ("n", ctypes.c_int64), ("c", ctypes.c_int64), ("h", ctypes.c_int64), ("w", ctypes.c_int64)]
+                ("n", ctypes.c_int64), ("c", ctypes.c_int64), ("h", ctypes.c_int64), ("w", ctypes.c_int64),
+                ("in1", ctypes.c_void_p)]
 
 
 class hf_pair(ctypes.Structure):
@@ -214,6 +216,33 @@ def task_maxpool(x, out, idx=None, kh: int = 3, kw: int = 3, stride: int = 2, pa
     t.p[0], t.p[1], t.p[2], t.p[3] = kh, kw, stride, pad
     t.in_, t.out0, t.out1 = _ptr(x), _ptr(out), _ptr(idx)
     t.n, t.c, t.h, t.w = x.shape
+    return t
+
+
+def _hash_task(kind, header, digests, nonce0: int, n: int) -> hf_task:
+    t = hf_task()
+    t.kind = kind
+    t.p[0] = ctypes.c_int32(nonce0 & 0xFFFFFFFF).value
+    t.in_, t.out0 = _ptr(header), _ptr(digests)
+    t.n = n
+    return t
+
+
+def task_sha256d(header, digests, nonce0: int, n: int) -> hf_task:
+    """SHA-256(SHA-256(header[0:76] || le32(nonce0 + i))) into digests[i] (32 bytes)."""
+    return _hash_task(HF_SHA256D, header, digests, nonce0, n)
+
+
+def task_blake2b(header, digests, nonce0: int, n: int) -> hf_task:
+    """32-byte BLAKE2b (no key) of header[0:76] || le32(nonce0 + i) into digests[i]."""
+    return _hash_task(HF_BLAKE2B, header, digests, nonce0, n)
+
+
+def task_ethash(header, table, digests, nonce0: int, n: int) -> hf_task:
+    """Ethash-like digests over `table` (uint32 [rows][32])."""
+    t = _hash_task(HF_ETHASH, header, digests, nonce0, n)
+    t.in1 = _ptr(table)
+    t.h = table.shape[0]
     return t
 
 

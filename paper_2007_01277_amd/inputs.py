@@ -12,6 +12,8 @@ the synthetic stand-ins for its PyTorch and mining workloads):
   * integer mixing seeds: uniform uint32
   * histogram input: uint8 values from a Zipf law with exponent 1.2 truncated to
     ranks 1..256 (value = rank - 1), drawn by inverse CDF
+  * hash kernels: an 80-byte block header of uniform bytes and a first nonce
+    of uniform uint32; the Ethash-like table: uniform uint32 rows of 32 words
 """
 from __future__ import annotations
 
@@ -75,6 +77,20 @@ def uniform_u8(n: int, seed: int = 0) -> np.ndarray:
 # timing workloads; the same distributions as above, different streams of
 # numbers.  Tests copy the device values back to the host before checking them
 # against the oracle.
+def header80(seed: int = 0) -> np.ndarray:
+    """An 80-byte block header (uint8)."""
+    return rng(seed).integers(0, 256, size=80, dtype=np.uint8)
+
+
+def nonce0(seed: int = 0) -> int:
+    return int(rng(seed + 1).integers(0, 2 ** 32, dtype=np.uint64))
+
+
+def eth_table(rows: int, seed: int = 0) -> np.ndarray:
+    """The synthetic table of the Ethash-like kernel: uint32 [rows][32]."""
+    return rng(seed).integers(0, 2 ** 32, size=(rows, 32), dtype=np.uint64).astype(np.uint32)
+
+
 def cuda_generator(seed: int):
     import torch
     g = torch.Generator(device="cuda")
@@ -97,3 +113,10 @@ def cuda_zipf_u8(n: int, seed: int, s: float = 1.2):
     cdf = torch.from_numpy(zipf_cdf(s)).to("cuda")
     u = torch.rand(n, generator=cuda_generator(seed), device="cuda", dtype=torch.float64)
     return torch.clamp(torch.searchsorted(cdf, u, right=True), max=255).to(torch.uint8)
+
+
+def cuda_eth_table(rows: int, seed: int):
+    """A device table of uniform uint32 words [rows][32] (int32 storage)."""
+    import torch
+    return torch.randint(-2**31, 2**31 - 1, (rows, 32), generator=cuda_generator(seed), device="cuda",
+                         dtype=torch.int32)

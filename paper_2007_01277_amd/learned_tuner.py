@@ -1,8 +1,10 @@
 """Learned tuner: sample collection, training and regret against the exhaustive search.
 
-Workload: random pairs of two distinct kinds drawn from the six kernels, each
+Workload: random pairs of two distinct kinds drawn from the nine kernels, each
 of 2^k elements with k uniform in [16, 26] (image kinds as [2^k / 65536, 64, 32,
-32], integer mixing with 32 rounds, histogram bytes from the Zipf law).  For
+32], integer mixing with 32 rounds, histogram bytes from the Zipf law; the
+hashes count a SHA-256d or BLAKE2b instance as 64 elements and an Ethash-like
+instance, over a shared 1 GiB table, as 256).  For
 every pair the tuner's own profiler times every candidate of the exhaustive
 search (median of ``reps`` launches), and ``hf_featurize`` gives the model's
 features.  Cross-validation is by pair: the model is trained on a random subset
@@ -79,11 +81,35 @@ class Instance:
             o = torch.empty_like(s)
             self.bufs += [s, o]
             self.task = H.task_int_mix(s, o, 32)
+        elif kind in (H.HF_SHA256D, H.HF_BLAKE2B, H.HF_ETHASH):
+            # a hash does the work of about 64 (256 for the table walk) elements
+            hdr = torch.from_numpy(inputs.header80(seed).view(np.int32)).cuda()
+            m = n >> (8 if kind == H.HF_ETHASH else 6)
+            o = torch.empty((max(m, 1), 8), dtype=torch.int32, device="cuda")
+            self.bufs += [hdr, o]
+            if kind == H.HF_ETHASH:
+                tab = eth_table()
+                self.task = H.task_ethash(hdr, tab, o, inputs.nonce0(seed), m)
+            elif kind == H.HF_SHA256D:
+                self.task = H.task_sha256d(hdr, o, inputs.nonce0(seed), m)
+            else:
+                self.task = H.task_blake2b(hdr, o, inputs.nonce0(seed), m)
         else:
             x = inputs.cuda_zipf_u8(n, seed)
             o = torch.empty(256, dtype=torch.int32, device="cuda")
             self.bufs += [x, o]
             self.task = H.task_lds_hist(x, o)
+
+
+_ETH = []
+
+
+def eth_table():
+    """The Ethash-like table shared by every instance: 1 GiB, past the 256 MB
+    last-level cache, as a mining table is."""
+    if not _ETH:
+        _ETH.append(inputs.cuda_eth_table(1 << 23, 77))
+    return _ETH[0]
 
 
 def r0_config(kind_a: int, kind_b: int) -> H.hf_config:

@@ -5,16 +5,20 @@ Tolerances (written here, used by every GPU test):
   * integer and copy kernels (int_mix, lds_hist, im2col): bit-exact;
   * maxpool: bit-exact values (NaN where the oracle has NaN) and indices, since
     a maximum is one of its inputs;
+  * hash kernels (sha256d, blake2b, ethash): bit-exact digests;
   * bn_stats: |d mean| <= 1e-5 * (|mean| + sigma) and |d var| <= 1e-5 * var
     (a relative bound on the mean alone is ill-posed when the mean is ~0);
   * upsample: |d out| <= 1e-5 * sum_k |w_k x_k| over the four taps.
 """
 from __future__ import annotations
 
+import functools
+
 import numpy as np
 import torch
 
 import oracle
+from oracle import hashes as OH
 from paper_2007_01277_amd import hfuse as H
 from paper_2007_01277_amd import inputs
 
@@ -162,6 +166,52 @@ def pool_case(shape, k=(3, 3), s=2, p=1, seed=0, offset=0, with_idx=True, x=None
     return Case(t, {"in": xd, "outs": outs}, check, f"maxpool{tuple(shape)}k{k}s{s}p{p}+{offset}")
 
 
+@functools.lru_cache(maxsize=None)
+def _hash_ref(kind, hdr_bytes, nonce0, i, table_key):
+    if kind == H.HF_SHA256D:
+        return OH.sha256d(hdr_bytes, nonce0, [i])[0]
+    if kind == H.HF_BLAKE2B:
+        return OH.blake2b_header(hdr_bytes, nonce0, [i])[0]
+    rows, seed = table_key
+    return OH.ethash_like_one(hdr_bytes, nonce0 + i, _eth_table(rows, seed))
+
+
+@functools.lru_cache(maxsize=4)
+def _eth_table(rows, seed):
+    return inputs.eth_table(rows, seed)
+
+
+def hash_case(kind, n, seed=0, nonce0=None, rows=4099, sample=None) -> Case:
+    """n instances of a hash kind; the oracle checks every instance, or the first
+    and last 64 plus `sample` drawn ones."""
+    hdr = inputs.header80(seed)
+    n0 = inputs.nonce0(seed) if nonce0 is None else nonce0 & 0xFFFFFFFF
+    hd = dev(hdr.view(np.int32))
+    out = torch.full((max(n, 1), 8), 7, dtype=torch.int32, device=DEV)[:n]
+    tkey = None
+    if kind == H.HF_ETHASH:
+        tkey = (rows, seed + 5)
+        td = dev(_eth_table(*tkey).view(np.int32))
+        t = H.task_ethash(hd, td, out, n0, n)
+        bufs = {"in": hd, "table": td, "outs": [out]}
+    else:
+        t = (H.task_sha256d if kind == H.HF_SHA256D else H.task_blake2b)(hd, out, n0, n)
+        bufs = {"in": hd, "outs": [out]}
+
+    def check(outs):
+        got = outs[0].cpu().numpy().view(np.uint8).reshape(n, 32)
+        if sample is None:
+            idx = range(n)
+        else:
+            idx = np.unique(np.concatenate([np.arange(min(n, 64)), np.arange(max(0, n - 64), n),
+                                            inputs.rng(seed + 9).integers(0, max(n, 1), size=sample)]))
+        for i in idx:
+            ref = _hash_ref(kind, hdr.tobytes(), n0, int(i), tkey)
+            assert got[i].tobytes() == ref, (H.KIND_NAMES[kind], int(i))
+
+    return Case(t, bufs, check, f"{H.KIND_NAMES[kind]}({n},nonce0={n0:#x})")
+
+
 def small_cases(kind, seed=0):
     """Small cases of one kind covering several tiles and a ragged tail."""
     if kind == H.HF_BN_STATS:
@@ -178,6 +228,10 @@ def small_cases(kind, seed=0):
     if kind == H.HF_MAXPOOL:
         return [pool_case((2, 8, 24, 20), seed=seed), pool_case((1, 3, 9, 11), (2, 2), 2, 0, seed, offset=1),
                 pool_case((2, 2, 7, 13), (3, 2), 1, 1, seed, with_idx=False)]
+    if kind in (H.HF_SHA256D, H.HF_BLAKE2B, H.HF_ETHASH):
+        # several waves of work, a ragged tail, and a nonce range that wraps past 2^32
+        return [hash_case(kind, 1000, seed), hash_case(kind, 333, seed + 1, nonce0=0xFFFFFF00, rows=37),
+                hash_case(kind, 67, seed + 2, rows=1)]
     raise ValueError(kind)
 
 

@@ -95,6 +95,37 @@ def _pool(n=1, c=2, h=6, w=6, k=(3, 3, 2, 1), idx=True):
     return t
 
 
+def _hash(kind, n=100, rows=64):
+    t = H.hf_task()
+    t.kind = kind
+    t.p[0] = -5  # any uint32 nonce
+    t.in_, t.out0 = _fake_ptr(), _fake_ptr(1 << 20)
+    if kind == H.HF_ETHASH:
+        t.in1, t.h = _fake_ptr(1 << 22), rows
+    t.n = n
+    return t
+
+
+def test_hash_tasks_validation():
+    for k in (H.HF_SHA256D, H.HF_BLAKE2B, H.HF_ETHASH):
+        assert H.hf_validate_task(_hash(k)) == H.HF_OK
+        assert H.hf_validate_task(_hash(k, n=0)) == H.HF_OK
+        assert H.hf_scratch_bytes(_hash(k)) == 0
+        t = _hash(k)
+        t.out0 = _fake_ptr((1 << 20) + 8)  # digests must be 16-byte aligned
+        assert H.hf_validate_task(t) == H.HF_EINVAL
+        t = _hash(k)
+        t.in_ = None
+        assert H.hf_validate_task(t) == H.HF_EINVAL
+        assert H.hf_validate_task(_hash(k, n=1 << 28)) == H.HF_EINVAL  # 8 words per digest
+    assert H.hf_validate_task(_hash(H.HF_ETHASH, rows=0)) == H.HF_EINVAL
+    assert H.hf_validate_task(_hash(H.HF_ETHASH, rows=1 << 32)) == H.HF_EINVAL
+    assert H.hf_validate_task(_hash(H.HF_ETHASH, rows=(1 << 32) - 1)) == H.HF_OK
+    t = _hash(H.HF_ETHASH)
+    t.in1 = None
+    assert H.hf_validate_task(t) == H.HF_EINVAL
+
+
 def test_valid_tasks_pass():
     for t in (_bn(), _mix(), _hist(), _im2col(), _up(), _pool(), _pool(idx=False), _mix(n=0), _hist(n=0),
               _im2col(n=0), _up(n=0), _pool(n=0)):
@@ -108,7 +139,7 @@ def test_valid_tasks_pass():
     (_hist, dict(out0=None)),
     (_im2col, dict(h=1, w=1)),  # 3x3 without enough padding... still legal with pad 1
     (_up, dict(c=0)),
-    (_bn, dict(kind=7)), (_bn, dict(kind=-1)),
+    (_bn, dict(kind=len(H.KIND_NAMES))), (_bn, dict(kind=-1)),
 ])
 def test_bad_tasks_rejected(make, change):
     t = make()

@@ -6,6 +6,7 @@ import pytest
 import torch
 
 import oracle
+from oracle import hashes as OH
 from paper_2007_01277_amd import batch_bench as BB
 from paper_2007_01277_amd import hfuse as H
 
@@ -19,8 +20,23 @@ def _init():
     H.hf_init()
 
 
-def check_instance(kind, x, outs):
+def check_instance(kind, x, outs, meta=None):
     xh = x.cpu().numpy()
+    if kind in (H.HF_SHA256D, H.HF_BLAKE2B, H.HF_ETHASH):
+        nonce0, tab = meta
+        got = outs[0].cpu().numpy().view(np.uint8).reshape(-1, 32)
+        hdr = xh.view(np.uint8).tobytes()
+        idx = sorted(set([0, 1, len(got) - 1, len(got) // 2]))
+        if kind == H.HF_SHA256D:
+            ref = OH.sha256d(hdr, nonce0, idx)
+        elif kind == H.HF_BLAKE2B:
+            ref = OH.blake2b_header(hdr, nonce0, idx)
+        else:
+            T = tab.cpu().numpy().view(np.uint32)
+            ref = [OH.ethash_like_one(hdr, nonce0 + i, T) for i in idx]
+        for i, r in zip(idx, ref):
+            assert got[i].tobytes() == r, (H.KIND_NAMES[kind], i)
+        return
     if kind == H.HF_BN_STATS:
         m_ref, v_ref = oracle.bn_stats(xh)
         m = outs[0].cpu().numpy().astype(np.float64)
@@ -131,3 +147,22 @@ def test_full_batch_1000_instances():
     assert res["batch_equal"] and res["batch_graph_equal"]
     for i in np.random.default_rng(0).choice(1000, 25, replace=False):
         check_instance(kinds[i], w.ins[i], ref[i])
+
+
+def test_batch_with_hash_kinds():
+    """Batches holding hash instances run the hash-capable kernel variant: the
+    same bits as the solo launches, eager and from the graph."""
+    kinds, logs, groups = BB.draw(48, seed=15, kmin=10, kmax=14, kinds=tuple(range(len(H.KIND_NAMES))))
+    assert any(k >= H.HF_SHA256D for k in kinds)
+    w = BB.Workload(kinds, logs, seed=15)
+    ref = solo_reference(w)
+    for k, x, o, m in zip(kinds, w.ins, ref, w.meta):
+        check_instance(k, x, o, m)
+    for block in (256, 1024):
+        b = H.Batch(w.tasks, groups, None, block)
+        for graph in (False, True, True):
+            w.clear()
+            b.run(graph)
+            torch.cuda.synchronize()
+            assert BB.same(ref, w.snapshot()), (block, graph)
+        b.close()

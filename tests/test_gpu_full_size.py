@@ -81,3 +81,16 @@ def test_maxpool_hist_full_size():
         outs = _fused_vs_serial(ca, cb, cfg)
     ca.check(outs[:2])
     cb.check(outs[2:])
+
+
+def test_ethash_sha256d_full_size():
+    """The crypto pair at the bench's sizes (327,680 Ethash-like hashes over a
+    1 GiB table, 2^22 SHA-256d hashes): fused bit-exact vs back to back over
+    every digest, sampled digests against the oracle."""
+    ca = G.hash_case(H.HF_ETHASH, 5 << 16, seed=21, rows=1 << 23, sample=48)
+    cb = G.hash_case(H.HF_SHA256D, 1 << 22, seed=21, sample=96)
+    for cfg in [(8, 1024, 0), (4, 512, 64), (1, 256, 128)]:
+        print("ethash 327680 + sha256d 2^22", cfg, flush=True)
+        outs = _fused_vs_serial(ca, cb, cfg)
+    ca.check(outs[:1])
+    cb.check(outs[1:])
