@@ -10,6 +10,10 @@ of this library, each with one kernel fixed and the other varied:
   bn_stats* [N,256,56,56]          + lds_hist 2^26 Zipf bytes, N = 4 .. 128
   im2col [32,128,56,56] 3x3        + lds_hist* 2^22 .. 2^28 Zipf bytes
   upsample x2 [32,64,128,128]      + lds_hist* 2^22 .. 2^28 Zipf bytes
+  maxpool* [N,64,112,112] 3x3/s2   + lds_hist 2^26 Zipf bytes, N = 4 .. 128
+  ethash* 2^15 .. 2^20 hashes      + sha256d 2^22 hashes (1 GiB table)
+  blake2b* 2^20 .. 2^24 hashes     + ethash 327,680 hashes
+  sha256d 2^22 hashes              + blake2b* 2^20 .. 2^24 hashes
 
 Methods at each point: HFuse = the exhaustive tuner's fused configuration;
 Naive = even split of a 1024-lane workgroup without a bound (Sec. IV-A); VFuse =
@@ -123,8 +127,56 @@ def main(argv=None):
             print(name, k, p["ratio_star_over_other"], p["speedup_pct"], flush=True)
             del hk
         res[name] = rows
+    # maxpool* (batch varied) + lds_hist fixed
+    rows = []
+    for N in (4, 8, 16, 32, 64, 128):
+        xp = inputs.cuda_normal((N, 64, 112, 112), 30)
+        osh = H.maxpool_out_shape((N, 64, 112, 112), 3, 3, 2, 1)
+        po, pi = torch.empty(osh, device="cuda"), torch.empty(osh, dtype=torch.int32, device="cuda")
+        p = point(H.make_pair(H.task_maxpool(xp, po, pi, 3, 3, 2, 1), hist), a.reps)
+        p["batch"] = N
+        p["ratio_star_over_other"] = round(p["t_a_ms"] / p["t_b_ms"], 3)
+        rows.append(p)
+        print("maxpool* + lds_hist", N, p["ratio_star_over_other"], p["speedup_pct"], flush=True)
+        del xp, po, pi
+    res["maxpool*+lds_hist"] = rows
+    del h, xi, cols, xu, up_out
+    torch.cuda.empty_cache()
+
+    # the crypto pairs
+    hdr = torch.from_numpy(inputs.header80(31).view(np.int32)).cuda()
+    table = inputs.cuda_eth_table(1 << 23, 32)
+    n0 = inputs.nonce0(31)
+
+    def hashes(kind, n):
+        o = torch.empty((n, 8), dtype=torch.int32, device="cuda")
+        if kind == H.HF_ETHASH:
+            return H.task_ethash(hdr, table, o, n0, n), o
+        return (H.task_sha256d if kind == H.HF_SHA256D else H.task_blake2b)(hdr, o, n0, n), o
+
+    sha, sha_o = hashes(H.HF_SHA256D, 1 << 22)
+    rows = []
+    for k in (15, 16, 17, 18, 19, 20):
+        et, eo = hashes(H.HF_ETHASH, 1 << k)
+        p = point(H.make_pair(et, sha), a.reps)
+        p["log2_hashes"] = k
+        p["ratio_star_over_other"] = round(p["t_a_ms"] / p["t_b_ms"], 3)
+        rows.append(p)
+        print("ethash* + sha256d", k, p["ratio_star_over_other"], p["speedup_pct"], flush=True)
+    res["ethash*+sha256d"] = rows
+    eth, eth_o = hashes(H.HF_ETHASH, 5 << 16)
+    for name, other in (("blake2b*+ethash", eth), ("sha256d+blake2b*", sha)):
+        rows = []
+        for k in (20, 21, 22, 23, 24):
+            bt, bo = hashes(H.HF_BLAKE2B, 1 << k)
+            p = point(H.make_pair(bt, other), a.reps)
+            p["log2_hashes"] = k
+            p["ratio_star_over_other"] = round(p["t_a_ms"] / p["t_b_ms"], 3)
+            rows.append(p)
+            print(name, k, p["ratio_star_over_other"], p["speedup_pct"], flush=True)
+        res[name] = rows
     summary = {}
-    for name, rows in res.items():
+    for name, rows in list(res.items()):
         summary[name] = {m: round(float(np.mean([r["speedup_pct"][m] for r in rows])), 2)
                          for m in ("hfuse", "naive", "vfuse", "streams")}
     res["mean_speedup_pct"] = summary
