@@ -8,8 +8,8 @@ instance, over a shared 1 GiB table, as 256).  For
 every pair the tuner's own profiler times every candidate of the exhaustive
 search (median of ``reps`` launches), and ``hf_featurize`` gives the model's
 features.  Cross-validation is by pair: the model is trained on a random subset
-of ``per_pair`` configurations of each training pair (200 pairs x 14 = about
-2100 training samples per fold at the defaults: the sample budget is spread
+of ``per_pair`` configurations of each training pair (600 pairs x 14 = about
+6300 training samples per fold at the defaults: the sample budget is spread
 over many pairs, which generalises far better than many configurations of few
 pairs) and judged on the held-out pairs, where it ranks all candidates and
 only the top k are "profiled" (their measured times are looked up).
@@ -216,7 +216,7 @@ def evaluate(data, folds: int = 4, per_pair: int = 14, topk: int = 3, epochs: in
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--pairs", type=int, default=200)
+    ap.add_argument("--pairs", type=int, default=600)
     ap.add_argument("--per-pair", type=int, default=14)
     ap.add_argument("--kmin", type=int, default=16)
     ap.add_argument("--kmax", type=int, default=26)
