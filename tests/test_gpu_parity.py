@@ -163,6 +163,26 @@ def test_edge_cases():
         G.run_and_check(lambda: H.hf_run_fused(pr, 1, 2, 256), [ca, cb])
 
 
+def test_edge_cases_pool_and_hashes():
+    # empty and one-element pooling and hash tasks, a 1x1 window, a window
+    # clipped to one element, solo and fused with each other and with a data kind
+    cases = [G.pool_case((0, 3, 4, 4)), G.pool_case((1, 1, 1, 1), (1, 1), 1, 0),
+             G.pool_case((1, 2, 1, 1), (3, 3), 2, 1, with_idx=False), G.pool_case((1, 1, 2, 3), (2, 2), 3, 1)]
+    for k in (H.HF_SHA256D, H.HF_BLAKE2B, H.HF_ETHASH):
+        cases += [G.hash_case(k, 0, seed=k), G.hash_case(k, 1, seed=k, rows=1)]
+    for c in cases:
+        print(c.label, flush=True)
+        G.run_and_check(lambda: H.hf_run_solo(c.task, 256), [c])
+    other = G.mix_case(5, 2, offset=1)
+    for ca, cb in itertools.combinations(cases, 2):
+        pr = H.make_pair(ca.task, cb.task)
+        G.run_and_check(lambda: H.hf_run_fused(pr, 1, 2, 256), [ca, cb])
+    for c in cases:
+        pr = H.make_pair(c.task, other.task)
+        G.run_and_check(lambda: H.hf_run_fused(pr, 3, 4, 256), [c, other])
+        G.run_and_check(lambda: H.hf_run_vfused(pr, 512), [c, other])
+
+
 def test_maxpool_ties_nan_and_clamped_windows():
     """Ties keep the first element, NaN propagates, and windows clipped by the
     padding match the oracle's scan -- solo and fused, with and without indices."""
