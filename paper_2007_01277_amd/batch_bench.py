@@ -1,9 +1,11 @@
 """Batched N-way fusion of many small instances: workload and benchmark.
 
-Workload: `count` instances; kind uniform over the five kernels; 2^k elements
-with k uniform in [kmin, kmax]; image kinds shaped [1, 16, 16, 2^k / 256]
-(im2col 3x3/s1/p1, upsample x2), integer mixing with 32 rounds, histogram bytes
-from the Zipf law.  Consecutive instances form groups of 2 to 4 (uniform).
+Workload: `count` instances; kind uniform over the six data kernels (the hash
+kinds can be drawn too, see ``draw``); 2^k elements with k uniform in
+[kmin, kmax]; image kinds shaped [1, 16, 16, 2^k / 256] (im2col 3x3/s1/p1,
+upsample x2, maxpool 3x3/s2/p1 with indices), integer mixing with 32 rounds,
+histogram bytes from the Zipf law; a hash instance counts as 64 elements.
+Consecutive instances form groups of 2 to 4 (uniform).
 Every instance has its own scratch region (so concurrent baselines cannot
 race), zero-filled at allocation.
 
