@@ -68,10 +68,10 @@ def copy_calibration(mib):
     return 0
 
 
-def traffic_from_profiles(kernel_key):
-    """HBM bytes per launch from the committed counter summary, if it was taken
-    on the current kernel sources; None otherwise."""
-    p = os.path.join(ROOT, "profiles", "traffic.json")
+def _profile_entry(fname, kernel_key):
+    """Entry of a committed counter record, if it was taken on the current
+    kernel sources; None otherwise."""
+    p = os.path.join(ROOT, "profiles", fname)
     if not os.path.exists(p):
         return None
     with open(p) as fh:
@@ -80,7 +80,33 @@ def traffic_from_profiles(kernel_key):
     e = d.get(kernel_key)
     if not e or e.get("csrc_hash") != csrc_hash():
         return None
-    return e["hbm_bytes_per_launch"]
+    return e
+
+
+def traffic_from_profiles(kernel_key):
+    """HBM bytes per launch of the fused kernel (FETCH_SIZE and WRITE_SIZE scaled
+    by the copy-kernel calibration), or None."""
+    e = _profile_entry("traffic.json", kernel_key)
+    return None if e is None else e["hbm_bytes_per_launch"]
+
+
+def valu_busy_from_profiles(kernel_key):
+    """VALUBusy (%) of the fused kernel from its rocprofv3 pass, or None."""
+    e = _profile_entry("counters.json", kernel_key)
+    return None if e is None else e.get("VALUBusy")
+
+
+def host_cpu():
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return f"{model or 'unknown CPU'}, {os.cpu_count()} hardware threads visible"
 
 
 class Workload:
@@ -190,7 +216,7 @@ class Workload:
             full = (t1 - t0) * self.n_eth / ke + (t2 - t1) * self.n_sha / ks
             return {"value": round(full * 1e3, 1), "unit": "ms/step", "cores": 1, "kind": "oracle",
                     "sample": f"{ke} Ethash-like and {ks} SHA-256d hashes ({(t2 - t0):.1f} s, single thread), "
-                              f"scaled to the step's {self.n_eth} + {self.n_sha} hashes"}
+                              f"scaled to the step's {self.n_eth} + {self.n_sha} hashes", "host": host_cpu()}
         if self.name == "bn_stats+int_mix":
             oracle.bn_stats(self.x)
             t1 = time.perf_counter()
@@ -209,7 +235,7 @@ class Workload:
         t2 = time.perf_counter()
         return {"value": round((t2 - t0) * 1e3, 2), "unit": "ms/step", "cores": 1, "kind": "oracle",
                 "sample": f"the full step ({parts}): {(t1 - t0) * 1e3:.0f} ms + {(t2 - t1) * 1e3:.0f} ms, "
-                          "single thread"}
+                          "single thread", "host": host_cpu()}
 
 
 def measure(w, cfg_arg, blocks_arg, steps, warmup, log=sys.stderr):
@@ -261,10 +287,29 @@ def measure(w, cfg_arg, blocks_arg, steps, warmup, log=sys.stderr):
         wall = (time.perf_counter() - t0) * 1e3 / steps
         return wall, [evs[i].elapsed_time(evs[i + 1]) for i in range(steps)]
 
+    def timed_cold(fn, reps):
+        """Per-step times with the 1 GiB scrub (untimed) before every step, so
+        no input is left in the 256 MB last-level cache."""
+        out = []
+        for _ in range(reps):
+            H.hf_scrub(stream)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            out.append(e0.elapsed_time(e1))
+        return float(np.median(out))
+
     fused_ms, fused_per = timed(run_fused)
     print(f"{w.name}: fused {fused_ms:.4f} ms/step", file=log, flush=True)
     serial_ms, _ = timed(run_serial)
     streams_ms, _ = timed(run_streams)
+    cold_reps = max(5, min(steps, 20))
+    cold = {"fused_ms": timed_cold(run_fused, cold_reps), "serial_ms": timed_cold(run_serial, cold_reps),
+            "reps": cold_reps}
+    cold["speedup_pct"] = round((cold["serial_ms"] / cold["fused_ms"] - 1.0) * 100.0, 3)
+    cold["fused_ms"], cold["serial_ms"] = round(cold["fused_ms"], 5), round(cold["serial_ms"], 5)
     solo_ms = [float(np.median([H.hf_run_solo(t, b, timed=True) for _ in range(21)]))
                for t, b in zip((w.ta, w.tb), blk)]
     # the timed configuration reproduces the back-to-back result bit for bit
@@ -275,7 +320,8 @@ def measure(w, cfg_arg, blocks_arg, steps, warmup, log=sys.stderr):
     torch.cuda.synchronize()
     bit_exact = all(torch.equal(p, q) for p, q in zip(f_out, w.outs))
     return {"cfg": cfg, "tune": tune, "blk": blk, "fused_ms": fused_ms, "fused_per": fused_per,
-            "serial_ms": serial_ms, "streams_ms": streams_ms, "solo_ms": solo_ms, "bit_exact": bit_exact}
+            "serial_ms": serial_ms, "streams_ms": streams_ms, "solo_ms": solo_ms, "bit_exact": bit_exact,
+            "cold": cold}
 
 
 def main():
@@ -315,7 +361,8 @@ def main():
         "config": {
             "workload": w.desc,
             "split_waves": cfg.split_waves, "block": cfg.block, "vgpr_cap": cfg.vgpr_cap,
-            "solo_blocks": m["blk"], "cache": "warm (no scrub between steps)",
+            "solo_blocks": m["blk"],
+            "cache": "warm (no scrub between steps); cold_cache: 1 GiB scrub before every step",
         },
         "fused_ms": round(m["fused_ms"], 5),
         "serial_ms": round(m["serial_ms"], 5),
@@ -325,7 +372,9 @@ def main():
                     H.KIND_NAMES[w.tb.kind]: round(m["solo_ms"][1], 5)},
         "ideal_speedup_pct": round((sum(m["solo_ms"]) / max(m["solo_ms"]) - 1.0) * 100.0, 3),
         "hbm_gbps": round(w.alg_bytes / (kernel_ms * 1e-3) / 1e9, 2),
-        "valu_busy": None,
+        "valu_busy": valu_busy_from_profiles("fused_" + w.name.replace("+", "_")),
+        "fused_step_ms_p10_p50_p90": [round(float(np.percentile(m["fused_per"], q)), 5) for q in (10, 50, 90)],
+        "cold_cache": m["cold"],
         "fused_bit_exact_vs_serial": m["bit_exact"],
     }
     key = "fused_" + w.name.replace("+", "_")
@@ -359,7 +408,10 @@ def main():
                 "speedup_vs_streams_pct": round((mo["streams_ms"] / mo["fused_ms"] - 1) * 100, 2),
                 "config": [mo["cfg"].split_waves, mo["cfg"].block, mo["cfg"].vgpr_cap],
                 "solo_blocks": mo["blk"], "bit_exact": mo["bit_exact"],
-                "hbm_gbps": round(o.alg_bytes / (float(np.mean(mo["fused_per"])) * 1e-3) / 1e9, 1)}
+                "hbm_gbps": round(o.alg_bytes / (float(np.mean(mo["fused_per"])) * 1e-3) / 1e9, 1),
+                "valu_busy": valu_busy_from_profiles("fused_" + name.replace("+", "_")),
+                "traffic": traffic_from_profiles("fused_" + name.replace("+", "_")),
+                "cold_cache": mo["cold"]}
             del o
             torch.cuda.empty_cache()
     print(json.dumps(res), flush=True)

@@ -2,13 +2,15 @@
 
   python -m paper_2007_01277_amd.rocprof_summary stats  --csv DIR/trace_kernel_stats.csv --cmd "..." --out profiles/X.md
   python -m paper_2007_01277_amd.rocprof_summary counters --dir DIR [--dir DIR ...] --match SUBSTR --cmd "..." --out profiles/Y.md
+         [--key NAME --key-match SUBSTR]
   python -m paper_2007_01277_amd.rocprof_summary traffic --fetch DIR --write DIR --copy-fetch DIR --copy-write DIR
          --copy-bytes B --match SUBSTR --key NAME --alg-bytes B --cmd "..." --out profiles/Z.md
 
 `traffic` scales the FETCH_SIZE / WRITE_SIZE counters (KiB per dispatch) of the
 matched kernel by what the same counters read for the library's copy kernel
 moving a known number of bytes, and records the result, with a hash of the
-kernel sources it was measured on, in profiles/traffic.json.
+kernel sources it was measured on, in profiles/traffic.json; `counters --key`
+records the matched kernel's counters the same way in profiles/counters.json.
 """
 from __future__ import annotations
 
@@ -74,11 +76,27 @@ def counters(a):
     lines = [f"# Counters: {a.title}", "", "Commands (from the repository root), one rocprofv3 pass each:", "", "```"]
     lines += a.cmd.split(";;")
     lines += ["```", "", "| kernel | counter | dispatches | mean per dispatch |", "|---|---|---:|---:|"]
+    entry = {}
     for d in a.dir:
         res = read_pmc(d)
         for n in pick(res, a.match):
             for c, v in sorted(res[n].items()):
                 lines.append(f"| `{short(n)}` | {c} | {len(v)} | {statistics.mean(v):.3f} |")
+        if a.key:
+            for n in pick(res, a.key_match):
+                for c, v in res[n].items():
+                    entry[c] = round(statistics.mean(v), 3)
+                entry.setdefault("kernel", [])
+                if short(n) not in entry["kernel"]:
+                    entry["kernel"].append(short(n))
+    if a.key:
+        # the fused kernel's counters, for the bench line (valid while the
+        # kernel sources hash matches)
+        entry["csrc_hash"] = csrc_hash()
+        path = os.path.join(ROOT, "profiles", "counters.json")
+        data = json.load(open(path)) if os.path.exists(path) else {}
+        data[a.key] = entry
+        json.dump(data, open(path, "w"), indent=1, sort_keys=True)
     if a.note:
         lines += ["", a.note]
     open(a.out, "w").write("\n".join(lines) + "\n")
@@ -136,6 +154,8 @@ def main():
     c = sub.add_parser("counters")
     c.add_argument("--dir", action="append", required=True)
     c.add_argument("--match", required=True)
+    c.add_argument("--key", default="", help="record the counters of --key-match in profiles/counters.json")
+    c.add_argument("--key-match", default="")
     c.add_argument("--cmd", required=True)
     c.add_argument("--out", required=True)
     c.add_argument("--title", default="")
