@@ -37,11 +37,15 @@ from . import inputs
 IMAGE = (64, 32, 32)  # C, H, W of the image kinds: 65536 elements per batch entry
 
 
-def draw_pairs(n_pairs: int, seed: int = 2, kmin: int = 16, kmax: int = 26):
+DATA_KINDS = (H.HF_BN_STATS, H.HF_UPSAMPLE, H.HF_IM2COL, H.HF_LDS_HIST, H.HF_INT_MIX)  # the five of the C4 set
+
+
+def draw_pairs(n_pairs: int, seed: int = 2, kmin: int = 16, kmax: int = 26, kinds=None):
+    kinds = np.asarray(range(len(H.KIND_NAMES)) if kinds is None else kinds)
     g = inputs.rng(seed)
     out = []
     for _ in range(n_pairs):
-        a, b = g.choice(len(H.KIND_NAMES), size=2, replace=False)
+        a, b = kinds[g.choice(len(kinds), size=2, replace=False)]
         ka, kb = g.integers(kmin, kmax + 1, size=2)
         out.append((int(a), int(b), int(ka), int(kb)))
     return out
@@ -227,12 +231,14 @@ def main(argv=None):
     ap.add_argument("--out", default="")
     ap.add_argument("--save-samples", default="")
     ap.add_argument("--collect-only", action="store_true")
+    ap.add_argument("--kinds", default="", help="comma-separated kind names to draw from (default: all nine)")
     a = ap.parse_args(argv)
+    kinds = [H.KIND_NAMES.index(k) for k in a.kinds.split(",")] if a.kinds else None
     import torch
     torch.cuda.set_device(0)
     H.hf_init()
     H.hf_warmup(300)
-    pairs = draw_pairs(a.pairs, kmin=a.kmin, kmax=a.kmax)
+    pairs = draw_pairs(a.pairs, kmin=a.kmin, kmax=a.kmax, kinds=kinds)
     data = collect(pairs, reps=a.reps)
     if a.save_samples:
         np.savez(a.save_samples, X=data["X"], y=data["y"], pair=data["pair"], cand=data["cand"],
