@@ -266,13 +266,14 @@ int hf_register_bound(int d1, int d2, int vgpr_a, int vgpr_b, int lds_fused);
  * (a, then b) a one-hot kind, log2 solo times at blocks 256/512/1024, log2
  * algorithmic bytes and lane-ops, and the fractions of HBM and integer-ALU
  * peak its best solo run reached; then the split fraction, block size, VGPR
- * bound, resident wavefronts per SIMD and four time estimates built from the
- * solo times and the split.  The tuner trains it on log2(fused time / sum of
+ * bound, resident wavefronts per SIMD, three time estimates built from the
+ * solo times and the split, the fused instantiation's spill bytes and VGPRs,
+ * and the sum of the best solo times.  The tuner trains it on log2(fused time / sum of
  * the best solo times); only the order of its predictions for one pair is
  * used.  Trained and evaluated on the GPU by the library's own kernels.  One
  * model per process, on the device current at hf_mlp_init.  Unless stated
  * otherwise, arrays are HOST pointers, row-major. */
-#define HF_MLP_FEATURES 40 /* 2 * (HF_NUM_KINDS + 7) + 8; the last is log2(sum of solo times) */
+#define HF_MLP_FEATURES 42 /* 2 * (HF_NUM_KINDS + 7) + 10; the last is log2(sum of solo times) */
 /* Allocates the model for d_in features: He-uniform weights from `seed`
  * (splitmix64), zero biases, identity feature standardisation. */
 int hf_mlp_init(int d_in, uint64_t seed);

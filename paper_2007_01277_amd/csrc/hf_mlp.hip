@@ -361,17 +361,19 @@ static int solo_feat(DeviceState* s, const hf_task* t, hipStream_t st, SoloFeat*
 //   per kernel (kPerKernel each): one-hot kind (HF_NUM_KINDS); log2 solo time
 //   at blocks 256, 512, 1024; log2 algorithmic MB and mega-lane-ops; fractions
 //   of the HBM and integer-ALU peaks the best solo run reached;
-//   configuration (8): split fraction s = 64*split_waves/block; log2(block/512);
+//   configuration (10): split fraction s = 64*split_waves/block; log2(block/512);
 //   VGPR bound / 128 (1 when unbounded); resident waves per SIMD / 8;
 //   log2(t_a(block)/s), log2(t_b(block)/(1-s)) and the log2 of their maximum,
-//   with t_k(block) the solo time at the candidate's block size; log2 of the
-//   sum of the best solo times (the last feature).
+//   with t_k(block) the solo time at the candidate's block size; the fused
+//   instantiation's spill bytes per lane (log2(1 + bytes) / 8) and VGPRs / 128;
+//   log2 of the sum of the best solo times (the last feature).
 constexpr int kPerKernel = HF_NUM_KINDS + 7;
 constexpr int kCfg = 2 * kPerKernel;
-static_assert(kCfg + 8 == kFeat, "feature layout and HF_MLP_FEATURES disagree");
+static_assert(kCfg + 10 == kFeat, "feature layout and HF_MLP_FEATURES disagree");
 
-static void fill_features(const SoloFeat& fa0, const SoloFeat& fb0, const hf_config& c, int waves_per_simd,
-                          float* x) {
+static void fill_features(const SoloFeat& fa0, const SoloFeat& fb0, const hf_config& c,
+                          const hf_kernel_info& fused, float* x) {
+  const int waves_per_simd = fused.waves_per_simd;
   auto l2 = [](double v) { return (float)std::log2(std::max(v, 1e-30)); };
   // canonical order: the kernel of the smaller kind first, with the split
   // fraction mirrored, so (a, b, s) and (b, a, 1 - s) -- the same fused kernel
@@ -404,7 +406,9 @@ static void fill_features(const SoloFeat& fa0, const SoloFeat& fb0, const hf_con
   g[4] = l2(ta);
   g[5] = l2(tb);
   g[6] = l2(std::max(ta, tb));
-  g[7] = l2(fa.t_ms + fb.t_ms);
+  g[7] = (float)(std::log2(1.0 + std::max(0, fused.spill_bytes)) / 8.0);
+  g[8] = fused.vgprs / 128.f;
+  g[9] = l2(fa.t_ms + fb.t_ms);
 }
 
 int featurize(DeviceState* s, const hf_pair* pr, const hf_config* cfg, int n, hipStream_t st, float* X) {
@@ -415,7 +419,7 @@ int featurize(DeviceState* s, const hf_pair* pr, const hf_config* cfg, int n, hi
   for (int i = 0; i < n; ++i) {
     hf_kernel_info info;
     if ((rc = hf_fused_info(pr->a.kind, pr->b.kind, cfg[i].block, cfg[i].vgpr_cap, &info)) != HF_OK) return rc;
-    fill_features(fa, fb, cfg[i], info.waves_per_simd, X + (size_t)i * kFeat);
+    fill_features(fa, fb, cfg[i], info, X + (size_t)i * kFeat);
   }
   return HF_OK;
 }

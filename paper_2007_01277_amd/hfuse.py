@@ -357,7 +357,7 @@ def hf_register_bound(d1: int, d2: int, vgpr_a: int, vgpr_b: int, lds_fused: int
 
 
 # ------------------------------------------------------------------ learned cost model
-MLP_FEATURES = 2 * (len(KIND_NAMES) + 7) + 8  # HF_MLP_FEATURES
+MLP_FEATURES = 2 * (len(KIND_NAMES) + 7) + 10  # HF_MLP_FEATURES
 
 
 def _f32(a):
