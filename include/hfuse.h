@@ -347,6 +347,16 @@ int hf_read(const void* src, int64_t bytes, void* stream, float* ms_out);
  * repetitions; the lines it leaves behind are clean, so the next kernel pays
  * no write-back for them. */
 int hf_scrub(void* stream);
+/* Self-test of the interval barrier (the replacement of a counted barrier for
+ * one interval of the workgroup, Sec. III-A "Replace Synchronization
+ * Barriers"): `grid` workgroups of `block` lanes (0: the resident count), split
+ * after `split_waves` wavefronts, run a ring exchange through LDS for iters_a
+ * and iters_b rounds, with pseudo-random skew per wavefront and round (from
+ * `seed`).  Writes the number of mismatched reads (0 when every barrier held)
+ * to the HOST pointer `mismatches`; waits for completion (HF_ETIMEOUT after
+ * HF_TIMEOUT_MS). */
+int hf_selftest_barrier(int block, int split_waves, int iters_a, int iters_b, uint32_t seed, int grid,
+                        void* stream, uint32_t* mismatches);
 /* Keeps the GPU busy for about `ms` milliseconds (warm-up before measurements,
  * Sec. IV-A "Execution Time Measurement"). */
 int hf_warmup(int ms, void* stream);

@@ -608,6 +608,58 @@ __global__ void __launch_bounds__(256) k_fill(float4* __restrict__ dst, uint64_t
     dst[i] = make_float4(v, v, v, v);
 }
 
+// The library's 64 KiB `warm` buffer: words [0, kSinkWords) are the sinks the
+// measurement kernels write (one per workgroup, practically never), the last
+// word is the barrier self-test's error counter.
+constexpr int kSinkWords = (1 << 14) - 1;
+
+// Interval-barrier self-test: both intervals of each workgroup run a ring
+// exchange through LDS.  In round r every wavefront sleeps a pseudo-random
+// 0..7 short intervals (so the wavefronts arrive skewed), writes a tag for
+// (r, its index) into its slot, syncs, reads its neighbour's slot, checks the
+// neighbour's tag, and syncs again before the next round's write.  The two
+// intervals run different round counts, so one finishes while the other still
+// synchronises.  Every wavefront of an interval calls sync() equally often.
+__device__ __forceinline__ uint32_t selftest_mix(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7FEB352Du;
+  x ^= x >> 15;
+  x *= 0x846CA68Bu;
+  x ^= x >> 16;
+  return x;
+}
+
+template <int BLOCK>
+__global__ void __launch_bounds__(BLOCK) k_barrier_selftest(uint32_t w1, uint32_t iters1, uint32_t iters2,
+                                                            uint32_t seed, uint32_t* errors) {
+  constexpr uint32_t W = BLOCK / 64;
+  __shared__ uint32_t ctr[2];
+  __shared__ uint32_t slots[W];
+  if (threadIdx.x == 0) {
+    ctr[0] = 0u;
+    ctr[1] = 0u;
+  }
+  __syncthreads();
+  const uint32_t wave = uniform(threadIdx.x >> 6);
+  const bool first = wave < w1;
+  const uint32_t nw = first ? w1 : W - w1;
+  const uint32_t k = first ? wave : wave - w1;
+  uint32_t* slot = first ? slots : slots + w1;
+  PartBarrier bar(first ? &ctr[0] : &ctr[1], nw);
+  const uint32_t iters = first ? iters1 : iters2;
+  const uint32_t nb = (k + 1u) % nw;
+  uint32_t bad = 0;
+  for (uint32_t r = 0; r < iters; ++r) {
+    const uint32_t skew = selftest_mix(seed ^ (blockIdx.x * 0x9E3779B1u) ^ (wave << 24) ^ r) & 7u;
+    for (uint32_t n = 0; n < skew; ++n) __builtin_amdgcn_s_sleep(1);
+    if (lane_id() == 0) slot[k] = selftest_mix(r * 0x01000193u ^ (k << 20) ^ blockIdx.x);
+    bar.sync();
+    if (slot[nb] != selftest_mix(r * 0x01000193u ^ (nb << 20) ^ blockIdx.x)) ++bad;
+    bar.sync();
+  }
+  if (bad) __hip_atomic_fetch_add(errors, bad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __global__ void __launch_bounds__(256) k_spin(uint32_t* sink, uint32_t iters) {
   uint32_t x = threadIdx.x ^ (blockIdx.x << 10);
   for (uint32_t i = 0; i < iters; ++i) x = IntMix::round1(x, i);
@@ -797,7 +849,7 @@ int hf_read(const void* src, int64_t bytes, void* stream, float* ms_out) {
   hipStream_t st = static_cast<hipStream_t>(stream);
   if ((rc = timed_begin(s, st, ms_out)) != HF_OK) return rc;
   const uint64_t n = (uint64_t)bytes / 16;
-  const int grid = std::max(1, std::min<int>((int)((n + 255) / 256), std::min(s->num_cus * 8, 16384)));
+  const int grid = std::max(1, std::min<int>((int)((n + 255) / 256), std::min(s->num_cus * 8, kSinkWords)));
   hipLaunchKernelGGL(k_read, dim3(grid), dim3(256), 0, st, static_cast<const float4*>(src), n,
                      static_cast<float*>(s->warm));
   hipError_t e = hipGetLastError();
@@ -830,10 +882,46 @@ int hf_scrub(void* stream) {
                        (uint64_t)(bytes / 16), 1.0f);
   }
   // one word per workgroup of sink: num_cus * 8 <= 16384 words of `warm`
-  hipLaunchKernelGGL(k_read, dim3(std::min(s->num_cus * 8, 16384)), dim3(256), 0, st,
+  hipLaunchKernelGGL(k_read, dim3(std::min(s->num_cus * 8, kSinkWords)), dim3(256), 0, st,
                      static_cast<const float4*>(s->scrub), (uint64_t)(bytes / 16), static_cast<float*>(s->warm));
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? HF_OK : record_hip(e);
+}
+
+int hf_selftest_barrier(int block, int split_waves, int iters_a, int iters_b, uint32_t seed, int grid,
+                        void* stream, uint32_t* mismatches) {
+  if (!mismatches || check_block(block) != HF_OK) return HF_EINVAL;
+  if (split_waves < 1 || split_waves >= block / 64) return HF_EINVAL;
+  if (iters_a < 0 || iters_b < 0 || iters_a > (1 << 20) || iters_b > (1 << 20)) return HF_EINVAL;
+  if (grid < 0 || grid > 65536) return HF_EINVAL;
+  int rc;
+  DeviceState* s = device_state(&rc);
+  if (!s) return rc;
+  if (!s->warm) {
+    hipError_t e = hipMalloc(&s->warm, 1 << 16);
+    if (e != hipSuccess) {
+      record_hip(e);
+      return HF_ENOMEM;
+    }
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  // the error counter: the word after the sinks of the 64 KiB buffer
+  uint32_t* errors = static_cast<uint32_t*>(s->warm) + kSinkWords;
+  hipError_t e = hipMemsetAsync(errors, 0, 4, st);
+  if (e != hipSuccess) return record_hip(e);
+  const void* fn = block == 256   ? reinterpret_cast<const void*>(&k_barrier_selftest<256>)
+                   : block == 512 ? reinterpret_cast<const void*>(&k_barrier_selftest<512>)
+                                  : reinterpret_cast<const void*>(&k_barrier_selftest<1024>);
+  if (grid == 0) {
+    if ((rc = occupancy_grid(s, fn, block, nullptr)) < 0) return rc;
+    grid = rc;
+  }
+  uint32_t w1 = (uint32_t)split_waves, ia = (uint32_t)iters_a, ib = (uint32_t)iters_b;
+  void* args[] = {&w1, &ia, &ib, &seed, &errors};
+  if ((e = hipLaunchKernel(fn, dim3(grid), dim3(block), args, 0, st)) != hipSuccess) return record_hip(e);
+  if ((e = hipMemcpyAsync(mismatches, errors, 4, hipMemcpyDeviceToHost, st)) != hipSuccess) return record_hip(e);
+  if ((e = hipEventRecord(s->ev_stop, st)) != hipSuccess) return record_hip(e);
+  return wait_event(s->ev_stop);
 }
 
 int hf_warmup(int ms, void* stream) {

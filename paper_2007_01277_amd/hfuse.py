@@ -117,6 +117,7 @@ SIGNATURES = {
     "hf_read": (_I, [_P, ctypes.c_int64, _P, _F]),
     "hf_scrub": (_I, [_P]),
     "hf_warmup": (_I, [_I, _P]),
+    "hf_selftest_barrier": (_I, [_I, _I, _I, _I, ctypes.c_uint32, _I, _P, ctypes.POINTER(ctypes.c_uint32)]),
 }
 
 _lib = None
@@ -522,6 +523,15 @@ def hf_read(src, nbytes: int, stream=None, timed=False):
 
 def hf_scrub(stream=None):
     _check(lib().hf_scrub(_stream(stream)), "hf_scrub")
+
+
+def hf_selftest_barrier(block: int, split_waves: int, iters_a: int, iters_b: int, seed: int = 0, grid: int = 0,
+                        stream=None) -> int:
+    """Interval-barrier self-test; returns the number of mismatched reads."""
+    m = ctypes.c_uint32(0)
+    _check(lib().hf_selftest_barrier(block, split_waves, iters_a, iters_b, seed & 0xFFFFFFFF, grid,
+                                     _stream(stream), ctypes.byref(m)), "hf_selftest_barrier")
+    return m.value
 
 
 def hf_warmup(ms: int = 500, stream=None):

@@ -258,3 +258,14 @@ def test_batch_create_rejects_bad_groups_before_the_gpu():
     assert call([0, 0, 1, 1, 2, 2], [2, 3, 1, 1, 1, 1]) == H.HF_EINVAL  # 5 waves > 4
     assert call([0, 0, 1, 1, 2, 2], [0, 1, 1, 1, 1, 1]) == H.HF_EINVAL  # a task without waves
     assert call([0, 0, 1, 1, 2, 2], None, block=384) == H.HF_EINVAL
+
+
+def test_barrier_selftest_rejects_bad_arguments():
+    # checked on the host before any HIP call
+    m = ctypes.c_uint32(0)
+    L = H.lib()
+    for args in [(128, 1, 1, 1), (256, 0, 1, 1), (256, 4, 1, 1), (1024, 16, 1, 1), (512, 2, -1, 1),
+                 (512, 2, 1, (1 << 20) + 1)]:
+        assert L.hf_selftest_barrier(*args, 0, 0, None, ctypes.byref(m)) == H.HF_EINVAL, args
+    assert L.hf_selftest_barrier(256, 1, 1, 1, 0, -1, None, ctypes.byref(m)) == H.HF_EINVAL
+    assert L.hf_selftest_barrier(256, 1, 1, 1, 0, 0, None, None) == H.HF_EINVAL

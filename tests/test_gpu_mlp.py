@@ -106,11 +106,12 @@ def test_training_fits_a_smooth_target_and_roundtrips_through_a_file():
 
 
 def test_learned_tuner_beats_the_untuned_choice():
-    """Trains on tuner-profiled samples of 75 pairs (14 configurations each) and
-    ranks every candidate of 25 held-out pairs: the model's top-3 choice has a
-    lower regret than the even split (the method without the network) and than
-    3 candidates profiled at random, at 3/85 of the exhaustive search's cost."""
-    pairs = LT.draw_pairs(100, seed=5, kmin=16, kmax=22)
+    """On pairs of the five data kernels (the learned-tuner workload): trains on
+    tuner-profiled samples of 75 pairs (14 configurations each) and ranks every
+    candidate of 25 held-out pairs: the model's top-3 choice has a lower regret
+    than the even split (the method without the network) and than 3 candidates
+    profiled at random, at 3/85 of the exhaustive search's cost."""
+    pairs = LT.draw_pairs(100, seed=5, kmin=16, kmax=22, kinds=LT.DATA_KINDS)
     data = LT.collect(pairs, reps=5, seed=5)
     res = LT.evaluate(data, folds=4, per_pair=14, topk=3, epochs=500)
     print({k: v for k, v in res.items() if k != "per_pair"}, flush=True)

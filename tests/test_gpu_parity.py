@@ -220,3 +220,15 @@ def test_hist_totals_equal_n():
     pr = H.make_pair(other.task, c.task)
     G.run_and_check(lambda: H.hf_run_fused(pr, 7, 8, 1024, 64), [c, other])
     assert int(c.outputs()[0].to(torch.int64).sum()) == 3_000_017
+
+
+@pytest.mark.parametrize("block", BLOCKS)
+def test_interval_barrier_stress(block):
+    """Ring exchange through LDS in both intervals of every workgroup, with
+    pseudo-random skew per wavefront and round, at every split; equal and
+    unequal round counts (one interval finishes while the other still syncs)."""
+    W = block // 64
+    for w1 in range(1, W):
+        for ia, ib, grid in [(64, 64, 0), (97, 13, 0), (5, 120, 1), (40, 40, 4096)]:
+            bad = H.hf_selftest_barrier(block, w1, ia, ib, seed=block * 131 + w1, grid=grid)
+            assert bad == 0, (block, w1, ia, ib, grid, bad)
