@@ -26,6 +26,7 @@ from __future__ import annotations
 import argparse
 import json
 import math
+import os
 import sys
 import time
 
@@ -126,20 +127,58 @@ def r0_config(kind_a: int, kind_b: int) -> H.hf_config:
     return H.hf_config(8, 1024, cap, 0)
 
 
-def collect(pairs, reps: int = 10, seed: int = 2, log=sys.stderr):
+def _store_key(p, pair, seed, reps):
+    """Key of one pair's samples: position, kinds, sizes, seed, repetitions and
+    the hash of the kernel sources they were measured on."""
+    from .rocprof_summary import csrc_hash
+    ka, kb, ea, eb = pair
+    return f"{p}:{ka},{kb},{ea},{eb}:seed{seed}:reps{reps}:{csrc_hash()}"
+
+
+def _load_store(path):
+    done = {}
+    if path and os.path.exists(path):
+        with open(path) as fh:
+            for ln in fh:
+                try:
+                    r = json.loads(ln)
+                except ValueError:  # a line cut short by an interrupted run
+                    continue
+                done[r["key"]] = r
+    return done
+
+
+def collect(pairs, reps: int = 10, seed: int = 2, log=sys.stderr, store: str = ""):
     """Profiles every exhaustive candidate of every pair; returns a dict of
-    numpy arrays (features X, log2 times y, pair index, candidate index)."""
+    numpy arrays (features X, log2 times y, pair index, candidate index).
+    With `store`, each pair's samples are appended to that JSON-lines file as
+    soon as they are measured, and pairs already in it (same key, see
+    _store_key) are read back instead of profiled again, so an interrupted
+    sweep resumes where it stopped."""
     import torch
     cands = H.hf_tune_candidates(H.HF_TUNE_EXHAUSTIVE, 0)
     keys = [c.as_tuple() for c in cands]
     Xs, ys, pid, cid = [], [], [], []
+    done = _load_store(store)
     t0 = time.time()
     for p, (ka, kb, ea, eb) in enumerate(pairs):
+        key = _store_key(p, (ka, kb, ea, eb), seed, reps)
+        if key in done:
+            X = np.asarray(done[key]["X"], np.float32)
+            y = np.asarray(done[key]["y"], np.float64)
+            Xs.append(X)
+            ys.append(y)
+            pid += [p] * len(cands)
+            cid += list(range(len(cands)))
+            continue
         ia = Instance(ka, ea, seed * 1000 + 2 * p)
         ib = Instance(kb, eb, seed * 1000 + 2 * p + 1)
         pr = H.make_pair(ia.task, ib.task)
         X = H.hf_featurize(pr, cands)
         y = np.array([math.log2(H.hf_profile(pr, c, reps)) for c in cands])
+        if store:
+            with open(store, "a") as fh:
+                fh.write(json.dumps({"key": key, "X": X.tolist(), "y": y.tolist()}) + "\n")
         Xs.append(X)
         ys.append(y)
         pid += [p] * len(cands)
@@ -230,6 +269,7 @@ def main(argv=None):
     ap.add_argument("--epochs", type=int, default=500)
     ap.add_argument("--out", default="")
     ap.add_argument("--save-samples", default="")
+    ap.add_argument("--store", default="", help="JSON-lines sample store: append as measured, resume from it")
     ap.add_argument("--collect-only", action="store_true")
     ap.add_argument("--kinds", default="", help="comma-separated kind names to draw from (default: all nine)")
     a = ap.parse_args(argv)
@@ -239,7 +279,7 @@ def main(argv=None):
     H.hf_init()
     H.hf_warmup(300)
     pairs = draw_pairs(a.pairs, kmin=a.kmin, kmax=a.kmax, kinds=kinds)
-    data = collect(pairs, reps=a.reps)
+    data = collect(pairs, reps=a.reps, store=a.store)
     if a.save_samples:
         np.savez(a.save_samples, X=data["X"], y=data["y"], pair=data["pair"], cand=data["cand"],
                  cands=np.array(data["cands"]), pairs=np.array(pairs))

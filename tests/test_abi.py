@@ -269,3 +269,12 @@ def test_barrier_selftest_rejects_bad_arguments():
         assert L.hf_selftest_barrier(*args, 0, 0, None, ctypes.byref(m)) == H.HF_EINVAL, args
     assert L.hf_selftest_barrier(256, 1, 1, 1, 0, -1, None, ctypes.byref(m)) == H.HF_EINVAL
     assert L.hf_selftest_barrier(256, 1, 1, 1, 0, 0, None, None) == H.HF_EINVAL
+
+
+def test_tuner_sample_store_skips_a_cut_line(tmp_path):
+    from paper_2007_01277_amd import learned_tuner as LT
+    p = tmp_path / "s.jsonl"
+    p.write_text('{"key": "a", "X": [[1.0]], "y": [0.5]}\n{"key": "b", "X": [[')
+    d = LT._load_store(str(p))
+    assert list(d) == ["a"] and d["a"]["y"] == [0.5]
+    assert LT._load_store(str(tmp_path / "missing.jsonl")) == {}

@@ -130,3 +130,23 @@ def test_hf_tune_mlp_profiles_only_topk():
     best, st = H.hf_tune(pr, H.HF_TUNE_MLP, 0, 3)
     assert st["n_profiled"] == 3 and st["n_candidates"] == 85
     assert H.hf_validate_fused(pr, best) == H.HF_OK
+
+
+def test_sample_store_resumes_an_interrupted_sweep(tmp_path, monkeypatch):
+    """Samples are appended per pair as measured; a second sweep over the same
+    pairs reads them back and profiles only the pair whose line was cut."""
+    pairs = LT.draw_pairs(3, seed=9, kmin=16, kmax=18, kinds=LT.DATA_KINDS)
+    st = str(tmp_path / "samples.jsonl")
+    a = LT.collect(pairs, reps=2, seed=9, store=st)
+    lines = open(st).read().splitlines(True)
+    assert len(lines) == 3
+    open(st, "w").write("".join(lines[:2]) + lines[2][:40])  # as an interrupted run leaves it
+    calls = []
+    real = LT.H.hf_profile
+    monkeypatch.setattr(LT.H, "hf_profile", lambda *x, **k: calls.append(1) or real(*x, **k))
+    b = LT.collect(pairs, reps=2, seed=9, store=st)
+    n = len(H.hf_tune_candidates(H.HF_TUNE_EXHAUSTIVE, 0))
+    assert len(calls) == n  # only the third pair again
+    np.testing.assert_array_equal(a["X"][:2 * n], b["X"][:2 * n])
+    np.testing.assert_array_equal(a["y"][:2 * n], b["y"][:2 * n])
+    assert len(open(st).read().splitlines()) == 4  # the cut line stays, the new one is appended

@@ -232,3 +232,20 @@ def test_interval_barrier_stress(block):
         for ia, ib, grid in [(64, 64, 0), (97, 13, 0), (5, 120, 1), (40, 40, 4096)]:
             bad = H.hf_selftest_barrier(block, w1, ia, ib, seed=block * 131 + w1, grid=grid)
             assert bad == 0, (block, w1, ia, ib, grid, bad)
+
+
+def test_timeout_returns_etimeout_and_the_kernel_still_completes(monkeypatch):
+    """The watchdog path: with HF_TIMEOUT_MS = 1 a timed launch of a ~14 ms
+    kernel returns HF_ETIMEOUT instead of blocking; the kernel itself runs to
+    completion (nothing is cancelled) and its output is correct."""
+    c = G.mix_case(1 << 24, 4096, seed=3, sample=256)
+    c.reset()
+    torch.cuda.synchronize()
+    monkeypatch.setenv("HF_TIMEOUT_MS", "1")
+    with pytest.raises(H.HFError) as err:
+        H.hf_run_solo(c.task, 256, timed=True)
+    assert err.value.status == H.HF_ETIMEOUT
+    monkeypatch.delenv("HF_TIMEOUT_MS")
+    torch.cuda.synchronize()
+    c.check(c.outputs())
+    assert H.hf_run_solo(c.task, 256, timed=True) > 1.0  # the library is usable afterwards
