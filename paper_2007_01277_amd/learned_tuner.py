@@ -148,6 +148,18 @@ def _load_store(path):
     return done
 
 
+def _append(path, rec):
+    """Appends one JSON line; a line left unterminated by an interrupted run is
+    closed first, so the new record starts a line of its own."""
+    lead = ""
+    if os.path.exists(path) and os.path.getsize(path) > 0:
+        with open(path, "rb") as fh:
+            fh.seek(-1, os.SEEK_END)
+            lead = "" if fh.read(1) == b"\n" else "\n"
+    with open(path, "a") as fh:
+        fh.write(lead + json.dumps(rec) + "\n")
+
+
 def collect(pairs, reps: int = 10, seed: int = 2, log=sys.stderr, store: str = ""):
     """Profiles every exhaustive candidate of every pair; returns a dict of
     numpy arrays (features X, log2 times y, pair index, candidate index).
@@ -177,8 +189,7 @@ def collect(pairs, reps: int = 10, seed: int = 2, log=sys.stderr, store: str = "
         X = H.hf_featurize(pr, cands)
         y = np.array([math.log2(H.hf_profile(pr, c, reps)) for c in cands])
         if store:
-            with open(store, "a") as fh:
-                fh.write(json.dumps({"key": key, "X": X.tolist(), "y": y.tolist()}) + "\n")
+            _append(store, {"key": key, "X": X.tolist(), "y": y.tolist()})
         Xs.append(X)
         ys.append(y)
         pid += [p] * len(cands)

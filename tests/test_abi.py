@@ -278,3 +278,6 @@ def test_tuner_sample_store_skips_a_cut_line(tmp_path):
     d = LT._load_store(str(p))
     assert list(d) == ["a"] and d["a"]["y"] == [0.5]
     assert LT._load_store(str(tmp_path / "missing.jsonl")) == {}
+    LT._append(str(p), {"key": "c", "X": [[2.0]], "y": [1.5]})  # after the cut line, on a line of its own
+    d = LT._load_store(str(p))
+    assert sorted(d) == ["a", "c"] and len(p.read_text().splitlines()) == 3
