@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--blocks", type=str, default="", help="block_a,block_b: skip the solo block sweep")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle timing")
     ap.add_argument("--no-pairs", action="store_true", help="skip the summary of the other pairs")
+    ap.add_argument("--no-cold", action="store_true",
+                    help="skip the scrubbed-cache repeats (profiled runs: every traced launch is then a warm one)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run the reference copy kernel over this many MiB (counter calibration)")
     return ap.parse_args()
@@ -238,7 +240,7 @@ class Workload:
                           "single thread", "host": host_cpu()}
 
 
-def measure(w, cfg_arg, blocks_arg, steps, warmup, log=sys.stderr):
+def measure(w, cfg_arg, blocks_arg, steps, warmup, log=sys.stderr, cold=True):
     """Tunes (unless fixed), then times the fused, back-to-back and two-stream steps."""
     import numpy as np
     import torch
@@ -305,11 +307,14 @@ def measure(w, cfg_arg, blocks_arg, steps, warmup, log=sys.stderr):
     print(f"{w.name}: fused {fused_ms:.4f} ms/step", file=log, flush=True)
     serial_ms, _ = timed(run_serial)
     streams_ms, _ = timed(run_streams)
-    cold_reps = max(5, min(steps, 20))
-    cold = {"fused_ms": timed_cold(run_fused, cold_reps), "serial_ms": timed_cold(run_serial, cold_reps),
-            "reps": cold_reps}
-    cold["speedup_pct"] = round((cold["serial_ms"] / cold["fused_ms"] - 1.0) * 100.0, 3)
-    cold["fused_ms"], cold["serial_ms"] = round(cold["fused_ms"], 5), round(cold["serial_ms"], 5)
+    if cold:
+        cold_reps = max(5, min(steps, 20))
+        cold = {"fused_ms": timed_cold(run_fused, cold_reps), "serial_ms": timed_cold(run_serial, cold_reps),
+                "reps": cold_reps}
+        cold["speedup_pct"] = round((cold["serial_ms"] / cold["fused_ms"] - 1.0) * 100.0, 3)
+        cold["fused_ms"], cold["serial_ms"] = round(cold["fused_ms"], 5), round(cold["serial_ms"], 5)
+    else:
+        cold = None
     solo_ms = [float(np.median([H.hf_run_solo(t, b, timed=True) for _ in range(21)]))
                for t, b in zip((w.ta, w.tb), blk)]
     # the timed configuration reproduces the back-to-back result bit for bit
@@ -342,7 +347,7 @@ def main():
     print("generating inputs", file=sys.stderr, flush=True)
     w = Workload(a.workload)
     H.hf_warmup(500)
-    m = measure(w, a.cfg, a.blocks, a.steps, a.warmup)
+    m = measure(w, a.cfg, a.blocks, a.steps, a.warmup, cold=not a.no_cold)
     cfg = m["cfg"]
     kernel_ms = float(np.mean(m["fused_per"]))
     res = {
@@ -400,7 +405,7 @@ def main():
         res["other_pairs"] = {}
         for name in WORKLOADS[1:]:
             o = Workload(name)
-            mo = measure(o, "", "", a.steps, 2)
+            mo = measure(o, "", "", a.steps, 2, cold=not a.no_cold)
             res["other_pairs"][name] = {
                 "fused_ms": round(mo["fused_ms"], 5), "serial_ms": round(mo["serial_ms"], 5),
                 "streams_ms": round(mo["streams_ms"], 5),
