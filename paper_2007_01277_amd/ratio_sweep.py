@@ -14,6 +14,11 @@ of this library, each with one kernel fixed and the other varied:
   ethash* 2^15 .. 2^20 hashes      + sha256d 2^22 hashes (1 GiB table)
   blake2b* 2^20 .. 2^24 hashes     + ethash 327,680 hashes
   sha256d 2^22 hashes              + blake2b* 2^20 .. 2^24 hashes
+and (``--sets memmem``) the six pairs of two memory-bound data kernels, each
+with the first kernel at its bench shape and the second's batch N varied:
+  bn_stats [64,256,56,56]  + maxpool* / upsample* / im2col*
+  im2col [32,128,56,56]    + maxpool* / upsample*
+  maxpool [64,64,112,112]  + upsample*
 
 Methods at each point: HFuse = the exhaustive tuner's fused configuration;
 Naive = even split of a 1024-lane workgroup without a bound (Sec. IV-A); VFuse =
@@ -63,16 +68,80 @@ def point(pr, reps):
             "hfuse_vs_streams_pct": round((streams / hfuse - 1) * 100, 2)}
 
 
+def image_task(kind, N, seed, keep):
+    """A task of an image kind at its bench shape with batch N; the tensors it
+    uses are appended to `keep`."""
+    import torch
+    if kind == H.HF_BN_STATS:
+        x = inputs.cuda_normal((N, 256, 56, 56), seed)
+        m, v = torch.empty(256, device="cuda"), torch.empty(256, device="cuda")
+        keep += [x, m, v]
+        return H.task_bn_stats(x, m, v)
+    if kind == H.HF_IM2COL:
+        x = inputs.cuda_normal((N, 128, 56, 56), seed)
+        o = torch.empty((N, 128 * 9, 56 * 56), device="cuda")
+        keep += [x, o]
+        return H.task_im2col(x, o, 3, 3, 1, 1)
+    if kind == H.HF_UPSAMPLE:
+        x = inputs.cuda_normal((N, 64, 128, 128), seed)
+        o = torch.empty((N, 64, 256, 256), device="cuda")
+        keep += [x, o]
+        return H.task_upsample(x, o, 2)
+    x = inputs.cuda_normal((N, 64, 112, 112), seed)
+    osh = H.maxpool_out_shape((N, 64, 112, 112), 3, 3, 2, 1)
+    o, oi = torch.empty(osh, device="cuda"), torch.empty(osh, dtype=torch.int32, device="cuda")
+    keep += [x, o, oi]
+    return H.task_maxpool(x, o, oi, 3, 3, 2, 1)
+
+
+MEMMEM = [  # (fixed kind, its batch, varied kind, batches)
+    (H.HF_BN_STATS, 64, H.HF_MAXPOOL, (8, 16, 32, 64, 128)),
+    (H.HF_BN_STATS, 64, H.HF_UPSAMPLE, (4, 8, 16, 32)),
+    (H.HF_BN_STATS, 64, H.HF_IM2COL, (4, 8, 16, 32)),
+    (H.HF_IM2COL, 32, H.HF_MAXPOOL, (8, 16, 32, 64, 128)),
+    (H.HF_IM2COL, 32, H.HF_UPSAMPLE, (4, 8, 16, 32)),
+    (H.HF_MAXPOOL, 64, H.HF_UPSAMPLE, (4, 8, 16, 32)),
+]
+
+
+def memmem(res, reps):
+    import torch
+    for kf, nf, kv, batches in MEMMEM:
+        keep = []
+        fixed = image_task(kf, nf, 40 + kf, keep)
+        name = f"{H.KIND_NAMES[kf]}+{H.KIND_NAMES[kv]}*"
+        rows = []
+        for N in batches:
+            kv_keep = []
+            var = image_task(kv, N, 50 + kv, kv_keep)
+            p = point(H.make_pair(fixed, var), reps)
+            p["batch"] = N
+            p["ratio_star_over_other"] = round(p["t_b_ms"] / p["t_a_ms"], 3)
+            rows.append(p)
+            print(name, N, p["ratio_star_over_other"], p["speedup_pct"], flush=True)
+            del kv_keep, var
+            torch.cuda.empty_cache()
+        res[name] = rows
+        del keep, fixed
+        torch.cuda.empty_cache()
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--reps", type=int, default=15)
     ap.add_argument("--out", default="")
+    ap.add_argument("--sets", default="paper,memmem", help="comma-separated: paper, memmem")
     a = ap.parse_args(argv)
     import torch
     torch.cuda.set_device(0)
     H.hf_init()
     H.hf_warmup(300)
     res = {}
+    sets = a.sets.split(",")
+    if "memmem" in sets:
+        memmem(res, a.reps)
+    if "paper" not in sets:
+        return finish(res, a.out)
 
     def zipf(n, seed):
         return inputs.cuda_zipf_u8(n, seed)
@@ -175,14 +244,18 @@ def main(argv=None):
             rows.append(p)
             print(name, k, p["ratio_star_over_other"], p["speedup_pct"], flush=True)
         res[name] = rows
+    return finish(res, a.out)
+
+
+def finish(res, out):
     summary = {}
     for name, rows in list(res.items()):
         summary[name] = {m: round(float(np.mean([r["speedup_pct"][m] for r in rows])), 2)
                          for m in ("hfuse", "naive", "vfuse", "streams")}
     res["mean_speedup_pct"] = summary
     print(json.dumps(summary), flush=True)
-    if a.out:
-        json.dump(res, open(a.out, "w"), indent=1)
+    if out:
+        json.dump(res, open(out, "w"), indent=1)
     return 0
 
 
