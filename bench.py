@@ -92,10 +92,11 @@ def traffic_from_profiles(kernel_key):
     return None if e is None else e["hbm_bytes_per_launch"]
 
 
-def valu_busy_from_profiles(kernel_key):
-    """VALUBusy (%) of the fused kernel from its rocprofv3 pass, or None."""
+def valu_busy_from_profiles(kernel_key, native=False):
+    """VALUBusy (%) of the fused kernel from its rocprofv3 pass (native: of the
+    two solo kernels back to back, time-weighted), or None."""
     e = _profile_entry("counters.json", kernel_key)
-    return None if e is None else e.get("VALUBusy")
+    return None if e is None else e.get("native_VALUBusy" if native else "VALUBusy")
 
 
 def host_cpu():
@@ -378,6 +379,7 @@ def main():
         "ideal_speedup_pct": round((sum(m["solo_ms"]) / max(m["solo_ms"]) - 1.0) * 100.0, 3),
         "hbm_gbps": round(w.alg_bytes / (kernel_ms * 1e-3) / 1e9, 2),
         "valu_busy": valu_busy_from_profiles("fused_" + w.name.replace("+", "_")),
+        "valu_busy_back_to_back": valu_busy_from_profiles("fused_" + w.name.replace("+", "_"), native=True),
         "fused_step_ms_p10_p50_p90": [round(float(np.percentile(m["fused_per"], q)), 5) for q in (10, 50, 90)],
         "cold_cache": m["cold"],
         "fused_bit_exact_vs_serial": m["bit_exact"],

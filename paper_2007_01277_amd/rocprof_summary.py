@@ -40,6 +40,23 @@ def csrc_hash():
     return h.hexdigest()[:16]
 
 
+def time_weighted(values, times):
+    """Utilisation of kernels launched one after the other, aggregated over
+    their run: each kernel's value weighted by its elapsed time (the paper's
+    Native issue-slot column, Sec. IV-C, weighs by elapsed cycles)."""
+    return sum(v * t for v, t in zip(values, times)) / sum(times)
+
+
+def trace_avg_ns(csv_path, match):
+    """Average duration (ns) of the kernels matching `match` in a
+    --kernel-trace --stats summary CSV."""
+    rows = [r for r in csv.DictReader(open(csv_path)) if all(m in r["Name"] for m in match.split("&"))]
+    if not rows:
+        raise SystemExit(f"no kernel matches {match!r} in {csv_path}")
+    calls = sum(int(r["Calls"]) for r in rows)
+    return sum(float(r["AverageNs"]) * int(r["Calls"]) for r in rows) / calls
+
+
 def short(name: str) -> str:
     s = name.replace("hf::", "").replace("(DevTask, DevTask, unsigned int)", "").replace("(DevTask)", "")
     return s if len(s) <= 90 else s[:87] + "..."
@@ -96,6 +113,26 @@ def counters(a):
                 entry.setdefault("kernel", [])
                 if short(n) not in entry["kernel"]:
                     entry["kernel"].append(short(n))
+    if a.native:
+        # the two solo kernels run back to back: each counter aggregated over
+        # their run, weighted by their traced durations
+        ma, mb = a.native.split(";")
+        ta, tb = trace_avg_ns(a.trace_csv, ma), trace_avg_ns(a.trace_csv, mb)
+        per = {}
+        for d in a.dir:
+            res = read_pmc(d)
+            for m, t in ((ma, ta), (mb, tb)):
+                for n in pick(res, m):
+                    for c, v in res[n].items():
+                        per.setdefault(c, {})[m] = statistics.mean(v)
+        lines += ["", f"Back-to-back aggregate of the two solo kernels (time-weighted, {ta / 1e3:.1f} us and "
+                      f"{tb / 1e3:.1f} us from the kernel trace) next to the fused kernel:", "",
+                  "| counter | fused | solo kernels back to back |", "|---|---:|---:|"]
+        for c in sorted(per):
+            if len(per[c]) == 2:
+                nat = time_weighted([per[c][ma], per[c][mb]], [ta, tb])
+                entry["native_" + c] = round(nat, 3)
+                lines.append(f"| {c} | {entry.get(c, float('nan')):.3f} | {nat:.3f} |")
     if a.key:
         # the fused kernel's counters, for the bench line (valid while the
         # kernel sources hash matches)
@@ -163,6 +200,8 @@ def main():
     c.add_argument("--match", required=True)
     c.add_argument("--key", default="", help="record the counters of --key-match in profiles/counters.json")
     c.add_argument("--key-match", default="")
+    c.add_argument("--native", default="", help="SOLO_A;SOLO_B: also aggregate the two solo kernels")
+    c.add_argument("--trace-csv", default="", help="kernel-trace stats CSV giving the solo durations")
     c.add_argument("--cmd", required=True)
     c.add_argument("--out", required=True)
     c.add_argument("--title", default="")
