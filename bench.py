@@ -266,6 +266,19 @@ def measure(w, cfg_arg, blocks_arg, steps, warmup, log=sys.stderr, cold=True):
         cfg, tune = H.hf_tune(pr, H.HF_TUNE_EXHAUSTIVE)
         cfg = H.hf_config(cfg.split_waves, cfg.block, cfg.vgpr_cap, 0)
     print(f"{w.name}: fused config {cfg}", file=log, flush=True)
+    regcap = None
+    if tune is not None:
+        # the register bound's effect (the paper's RegCap vs N-RegCap rows):
+        # the best unbounded and the best bounded candidate of the search
+        cands = H.hf_tune_candidates(H.HF_TUNE_EXHAUSTIVE, 0)
+        prof = [(H.hf_profile(pr, c, 10), c) for c in cands]
+        regcap = {}
+        for name, sel in (("unbounded", lambda c: c.vgpr_cap == 0), ("bounded", lambda c: c.vgpr_cap > 0)):
+            t, c = min(((t, c) for t, c in prof if sel(c)), key=lambda x: x[0])
+            info = H.hf_fused_info(w.ta.kind, w.tb.kind, c.block, c.vgpr_cap)
+            regcap[name] = {"ms": round(t, 5), "config": [c.split_waves, c.block, c.vgpr_cap],
+                            "vgprs": info["vgprs"], "spill_bytes": info["spill_bytes"],
+                            "waves_per_simd": info["waves_per_simd"]}
 
     def run_fused():
         H.hf_run_fused_cfg(pr, cfg, stream)
@@ -327,7 +340,7 @@ def measure(w, cfg_arg, blocks_arg, steps, warmup, log=sys.stderr, cold=True):
     bit_exact = all(torch.equal(p, q) for p, q in zip(f_out, w.outs))
     return {"cfg": cfg, "tune": tune, "blk": blk, "fused_ms": fused_ms, "fused_per": fused_per,
             "serial_ms": serial_ms, "streams_ms": streams_ms, "solo_ms": solo_ms, "bit_exact": bit_exact,
-            "cold": cold}
+            "cold": cold, "regcap": regcap}
 
 
 def main():
@@ -382,6 +395,7 @@ def main():
         "valu_busy_back_to_back": valu_busy_from_profiles("fused_" + w.name.replace("+", "_"), native=True),
         "fused_step_ms_p10_p50_p90": [round(float(np.percentile(m["fused_per"], q)), 5) for q in (10, 50, 90)],
         "cold_cache": m["cold"],
+        "register_bound": m["regcap"],
         "fused_bit_exact_vs_serial": m["bit_exact"],
     }
     key = "fused_" + w.name.replace("+", "_")
@@ -418,7 +432,7 @@ def main():
                 "hbm_gbps": round(o.alg_bytes / (float(np.mean(mo["fused_per"])) * 1e-3) / 1e9, 1),
                 "valu_busy": valu_busy_from_profiles("fused_" + name.replace("+", "_")),
                 "traffic": traffic_from_profiles("fused_" + name.replace("+", "_")),
-                "cold_cache": mo["cold"]}
+                "cold_cache": mo["cold"], "register_bound": mo["regcap"]}
             del o
             torch.cuda.empty_cache()
     print(json.dumps(res), flush=True)
