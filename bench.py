@@ -43,7 +43,7 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", choices=WORKLOADS, default=WORKLOADS[0])
     ap.add_argument("--cfg", type=str, default="", help="split_waves,block,cap: skip the tuner")
     ap.add_argument("--blocks", type=str, default="", help="block_a,block_b: skip the solo block sweep")

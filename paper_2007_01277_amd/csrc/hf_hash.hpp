@@ -230,7 +230,7 @@ struct EthashLike {
   static constexpr uint32_t lds_words(int) { return 0; }
   static constexpr uint32_t kPrime = 16777619u;
   static constexpr uint32_t kOffset = 2166136261u;
-  static constexpr uint32_t kChains = 2;
+  static constexpr uint32_t kChains = 4;
   static constexpr uint32_t kPerWave = 8 * kChains;  // hashes per wavefront per step
 
   __device__ static __forceinline__ uint32_t fnv(uint32_t x, uint32_t y) { return (x * kPrime) ^ y; }

@@ -57,6 +57,27 @@ def trace_avg_ns(csv_path, match):
     return sum(float(r["AverageNs"]) * int(r["Calls"]) for r in rows) / calls
 
 
+def alone_avg_ns(trace_csv, match):
+    """Average duration (ns) of the dispatches of the kernels matching `match`
+    (substrings separated by '&') that overlap no other dispatch in time, from
+    a --kernel-trace per-dispatch CSV: launches on two concurrent streams are
+    left out, so the figure is the kernel's time when it runs alone."""
+    rows = [(int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"])
+            for r in csv.DictReader(open(trace_csv))]
+    rows.sort()
+    durs = []
+    for i, (s, e, name) in enumerate(rows):
+        if not all(m in name for m in match.split("&")):
+            continue
+        before = i > 0 and max(r[1] for r in rows[:i]) > s
+        after = i + 1 < len(rows) and rows[i + 1][0] < e
+        if not (before or after):
+            durs.append(e - s)
+    if not durs:
+        raise SystemExit(f"no dispatch of {match!r} runs alone in {trace_csv}")
+    return sum(durs) / len(durs)
+
+
 def short(name: str) -> str:
     s = name.replace("hf::", "").replace("(DevTask, DevTask, unsigned int)", "").replace("(DevTask)", "")
     return s if len(s) <= 90 else s[:87] + "..."
@@ -69,9 +90,25 @@ def stats(a):
     for r in rows:
         out.append(f"| `{short(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
                    f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} |")
+    if a.trace and a.timed:
+        skip, k = (int(v) for v in a.timed.split(","))
+        d = launches_us(a.trace, a.timed_match, skip, k)
+        out += ["", f"Dispatches {skip + 1}..{skip + k} of `{short(a.timed_match)}` in the per-dispatch trace "
+                f"(the {k} timed steps after {skip} warmup steps): avg {statistics.fmean(d):.2f} us, median {statistics.median(d):.2f} us, min {min(d):.2f} us, "
+                f"max {max(d):.2f} us."]
     if a.note:
         out += ["", a.note]
     open(a.out, "w").write("\n".join(out) + "\n")
+
+
+def launches_us(trace_csv, match, skip, k):
+    """Durations (us) of dispatches skip+1 .. skip+k, in start order, of the
+    kernels whose name contains `match`, from a --kernel-trace per-dispatch CSV."""
+    rows = [r for r in csv.DictReader(open(trace_csv)) if match in r["Kernel_Name"]]
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    if len(rows) < skip + k:
+        raise SystemExit(f"only {len(rows)} dispatches match {match!r} in {trace_csv}")
+    return [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in rows[skip:skip + k]]
 
 
 def read_pmc(d):
@@ -117,7 +154,10 @@ def counters(a):
         # the two solo kernels run back to back: each counter aggregated over
         # their run, weighted by their traced durations
         ma, mb = a.native.split(";")
-        ta, tb = trace_avg_ns(a.trace_csv, ma), trace_avg_ns(a.trace_csv, mb)
+        if a.trace_dispatch:
+            ta, tb = alone_avg_ns(a.trace_dispatch, ma), alone_avg_ns(a.trace_dispatch, mb)
+        else:
+            ta, tb = trace_avg_ns(a.trace_csv, ma), trace_avg_ns(a.trace_csv, mb)
         per = {}
         for d in a.dir:
             res = read_pmc(d)
@@ -126,7 +166,8 @@ def counters(a):
                     for c, v in res[n].items():
                         per.setdefault(c, {})[m] = statistics.mean(v)
         lines += ["", f"Back-to-back aggregate of the two solo kernels (time-weighted, {ta / 1e3:.1f} us and "
-                      f"{tb / 1e3:.1f} us from the kernel trace) next to the fused kernel:", "",
+                      f"{tb / 1e3:.1f} us from the kernel trace"
+                      f"{', launches that ran alone' if a.trace_dispatch else ''}) next to the fused kernel:", "",
                   "| counter | fused | solo kernels back to back |", "|---|---:|---:|"]
         for c in sorted(per):
             if len(per[c]) == 2:
@@ -190,6 +231,9 @@ def main():
     sub = ap.add_subparsers(dest="mode", required=True)
     s = sub.add_parser("stats")
     s.add_argument("--csv", required=True)
+    s.add_argument("--trace", default="", help="the per-dispatch kernel trace CSV of the same run")
+    s.add_argument("--timed", default="", help="W,K: also summarise dispatches W+1..W+K of --timed-match")
+    s.add_argument("--timed-match", default="")
     for p in (s,):
         p.add_argument("--cmd", required=True)
         p.add_argument("--out", required=True)
@@ -202,6 +246,8 @@ def main():
     c.add_argument("--key-match", default="")
     c.add_argument("--native", default="", help="SOLO_A;SOLO_B: also aggregate the two solo kernels")
     c.add_argument("--trace-csv", default="", help="kernel-trace stats CSV giving the solo durations")
+    c.add_argument("--trace-dispatch", default="",
+                   help="per-dispatch kernel trace CSV: solo durations from the launches that ran alone")
     c.add_argument("--cmd", required=True)
     c.add_argument("--out", required=True)
     c.add_argument("--title", default="")

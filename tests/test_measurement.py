@@ -40,3 +40,15 @@ def test_time_weighted_issue_slots_reproduce_table_ii_native(pair):
 def test_time_weighted_basics():
     assert RS.time_weighted([50.0, 50.0], [1.0, 3.0]) == 50.0
     assert RS.time_weighted([100.0, 0.0], [1.0, 3.0]) == 25.0
+
+
+def test_alone_average_leaves_out_concurrent_launches(tmp_path):
+    # A runs alone twice (10 and 30 ns); B overlaps C (two streams) and once runs alone
+    rows = [("A", 0, 10), ("B", 20, 40), ("C", 30, 50), ("A", 60, 90), ("B", 100, 104)]
+    f = tmp_path / "trace.csv"
+    f.write_text("Kernel_Name,Start_Timestamp,End_Timestamp\n" +
+                 "".join(f"{n},{s},{e}\n" for n, s, e in rows))
+    assert RS.alone_avg_ns(str(f), "A") == 20.0
+    assert RS.alone_avg_ns(str(f), "B") == 4.0
+    with pytest.raises(SystemExit):
+        RS.alone_avg_ns(str(f), "C")
