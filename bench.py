@@ -431,6 +431,7 @@ def main():
                 "solo_blocks": mo["blk"], "bit_exact": mo["bit_exact"],
                 "hbm_gbps": round(o.alg_bytes / (float(np.mean(mo["fused_per"])) * 1e-3) / 1e9, 1),
                 "valu_busy": valu_busy_from_profiles("fused_" + name.replace("+", "_")),
+                "valu_busy_back_to_back": valu_busy_from_profiles("fused_" + name.replace("+", "_"), native=True),
                 "traffic": traffic_from_profiles("fused_" + name.replace("+", "_")),
                 "cold_cache": mo["cold"], "register_bound": mo["regcap"]}
             del o

@@ -3,7 +3,7 @@
 The evaluation varies the input size of one kernel of each pair (the kernel
 marked "*") and reports every fusion method's speedup over the native
 execution at each resulting ratio of solo times (Sec. IV-A "Run Different
-Workload", Sec. IV-B).  This script does the same on one MI355X for four pairs
+Workload", Sec. IV-B).  This script does the same on one MI355X for eight pairs
 of this library, each with one kernel fixed and the other varied:
 
   bn_stats [64,256,56,56]         + int_mix* 2^24 elements, R = 1 .. 128 rounds
@@ -27,6 +27,9 @@ Serial = back to back.  Speedup % = (T_serial / T_method - 1) * 100; the ratio
 is t_star / t_other of the best solo times.
 
     python -m paper_2007_01277_amd.ratio_sweep --out gpurun_out/ratio.json
+
+``--sets`` picks the groups: ``data`` (the first five pairs), ``crypto`` (the
+three hash pairs), ``paper`` (both) and ``memmem``.
 """
 from __future__ import annotations
 
@@ -126,11 +129,48 @@ def memmem(res, reps):
         torch.cuda.empty_cache()
 
 
+def crypto(res, reps):
+    import torch
+    # the crypto pairs
+    hdr = torch.from_numpy(inputs.header80(31).view(np.int32)).cuda()
+    table = inputs.cuda_eth_table(1 << 23, 32)
+    n0 = inputs.nonce0(31)
+
+    def hashes(kind, n):
+        o = torch.empty((n, 8), dtype=torch.int32, device="cuda")
+        if kind == H.HF_ETHASH:
+            return H.task_ethash(hdr, table, o, n0, n), o
+        return (H.task_sha256d if kind == H.HF_SHA256D else H.task_blake2b)(hdr, o, n0, n), o
+
+    sha, sha_o = hashes(H.HF_SHA256D, 1 << 22)
+    rows = []
+    for k in (15, 16, 17, 18, 19, 20):
+        et, eo = hashes(H.HF_ETHASH, 1 << k)
+        p = point(H.make_pair(et, sha), reps)
+        p["log2_hashes"] = k
+        p["ratio_star_over_other"] = round(p["t_a_ms"] / p["t_b_ms"], 3)
+        rows.append(p)
+        print("ethash* + sha256d", k, p["ratio_star_over_other"], p["speedup_pct"], flush=True)
+    res["ethash*+sha256d"] = rows
+    eth, eth_o = hashes(H.HF_ETHASH, 5 << 16)
+    for name, other in (("blake2b*+ethash", eth), ("sha256d+blake2b*", sha)):
+        rows = []
+        for k in (20, 21, 22, 23, 24):
+            bt, bo = hashes(H.HF_BLAKE2B, 1 << k)
+            p = point(H.make_pair(bt, other), reps)
+            p["log2_hashes"] = k
+            p["ratio_star_over_other"] = round(p["t_a_ms"] / p["t_b_ms"], 3)
+            rows.append(p)
+            print(name, k, p["ratio_star_over_other"], p["speedup_pct"], flush=True)
+        res[name] = rows
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--reps", type=int, default=15)
     ap.add_argument("--out", default="")
-    ap.add_argument("--sets", default="paper,memmem", help="comma-separated: paper, memmem")
+    ap.add_argument("--sets", default="paper,memmem",
+                    help="comma-separated: paper (= data,crypto), data, crypto, memmem")
     a = ap.parse_args(argv)
     import torch
     torch.cuda.set_device(0)
@@ -138,9 +178,13 @@ def main(argv=None):
     H.hf_warmup(300)
     res = {}
     sets = a.sets.split(",")
+    if "paper" in sets:
+        sets += ["data", "crypto"]
     if "memmem" in sets:
         memmem(res, a.reps)
-    if "paper" not in sets:
+    if "data" not in sets:
+        if "crypto" in sets:
+            crypto(res, a.reps)
         return finish(res, a.out)
 
     def zipf(n, seed):
@@ -212,38 +256,8 @@ def main(argv=None):
     del h, xi, cols, xu, up_out
     torch.cuda.empty_cache()
 
-    # the crypto pairs
-    hdr = torch.from_numpy(inputs.header80(31).view(np.int32)).cuda()
-    table = inputs.cuda_eth_table(1 << 23, 32)
-    n0 = inputs.nonce0(31)
-
-    def hashes(kind, n):
-        o = torch.empty((n, 8), dtype=torch.int32, device="cuda")
-        if kind == H.HF_ETHASH:
-            return H.task_ethash(hdr, table, o, n0, n), o
-        return (H.task_sha256d if kind == H.HF_SHA256D else H.task_blake2b)(hdr, o, n0, n), o
-
-    sha, sha_o = hashes(H.HF_SHA256D, 1 << 22)
-    rows = []
-    for k in (15, 16, 17, 18, 19, 20):
-        et, eo = hashes(H.HF_ETHASH, 1 << k)
-        p = point(H.make_pair(et, sha), a.reps)
-        p["log2_hashes"] = k
-        p["ratio_star_over_other"] = round(p["t_a_ms"] / p["t_b_ms"], 3)
-        rows.append(p)
-        print("ethash* + sha256d", k, p["ratio_star_over_other"], p["speedup_pct"], flush=True)
-    res["ethash*+sha256d"] = rows
-    eth, eth_o = hashes(H.HF_ETHASH, 5 << 16)
-    for name, other in (("blake2b*+ethash", eth), ("sha256d+blake2b*", sha)):
-        rows = []
-        for k in (20, 21, 22, 23, 24):
-            bt, bo = hashes(H.HF_BLAKE2B, 1 << k)
-            p = point(H.make_pair(bt, other), a.reps)
-            p["log2_hashes"] = k
-            p["ratio_star_over_other"] = round(p["t_a_ms"] / p["t_b_ms"], 3)
-            rows.append(p)
-            print(name, k, p["ratio_star_over_other"], p["speedup_pct"], flush=True)
-        res[name] = rows
+    if "crypto" in sets:
+        crypto(res, a.reps)
     return finish(res, a.out)
 
 
