@@ -10,9 +10,12 @@ Zipf bytes; or the crypto pair: 327,680 Ethash-like hashes (64 random 128-byte
 rows each of a 1 GiB table) with 2^22 SHA-256d hashes of 80-byte headers.
 
 A step is one fused launch of the pair at the configuration the exhaustive
-tuner picks (split, workgroup size, VGPR bound); the same inputs are also run
-back to back (each kernel at its best solo workgroup size) and on two
-concurrent streams.  Inputs are resident in HBM before any timing starts.
+tuner picks (split, workgroup size, VGPR bound; default grid); the same inputs
+are also run back to back (each kernel at its best solo workgroup size) and on
+two concurrent streams.  ``grid_tuned`` repeats the comparison with the launch
+grid searched on both sides: the fused kernel by the tuner's grid mode, each
+solo kernel over (workgroup size, grid).  Inputs are resident in HBM before any
+timing starts.
 
 Prints one JSON line: metric = speedup of the fused launch over the back-to-back
 launches in percent, plus absolute times, HBM GB/s, the roofline of the fused
@@ -45,8 +48,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", choices=WORKLOADS, default=WORKLOADS[0])
-    ap.add_argument("--cfg", type=str, default="", help="split_waves,block,cap: skip the tuner")
-    ap.add_argument("--blocks", type=str, default="", help="block_a,block_b: skip the solo block sweep")
+    ap.add_argument("--cfg", type=str, default="", help="split_waves,block,cap[,grid]: skip the tuner")
+    ap.add_argument("--blocks", type=str, default="",
+                    help="block_a,block_b[,grid_a,grid_b]: skip the solo block and grid sweep")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle timing")
     ap.add_argument("--no-pairs", action="store_true", help="skip the summary of the other pairs")
     ap.add_argument("--no-cold", action="store_true",
@@ -249,27 +253,42 @@ def measure(w, cfg_arg, blocks_arg, steps, warmup, log=sys.stderr, cold=True):
     from paper_2007_01277_amd import hfuse as H
     stream = torch.cuda.current_stream()
     pr = w.pair
+    blk_g = sgrid_g = None
     if blocks_arg:
-        blk = [int(v) for v in blocks_arg.split(",")]
+        vals = [int(v) for v in blocks_arg.split(",")]
+        blk, sgrid = vals[:2], (vals[2:4] if len(vals) == 4 else [0, 0])
     else:
-        blk = []
+        # each kernel alone at its best workgroup size with the default grid
+        # (the headline protocol) and, for the grid-tuned comparison, at its best
+        # (workgroup size, grid) with the grid 2, 4 or 8 times the occupancy grid
+        blk, sgrid, blk_g, sgrid_g = [], [0, 0], [], []
         for t in (w.ta, w.tb):
-            times = {b: float(np.median([H.hf_run_solo(t, b, timed=True) for _ in range(15)]))
-                     for b in (256, 512, 1024)}
-            blk.append(min(times, key=times.get))
-    print(f"{w.name}: solo blocks {blk}", file=log, flush=True)
-    tune = None
+            times = {}
+            for b in (256, 512, 1024):
+                occ = H.hf_solo_info(t.kind, b)["default_grid"]
+                for mult in (0, 2, 4, 8):
+                    times[(b, occ * mult)] = float(np.median([H.hf_run_solo(t, b, occ * mult, timed=True)
+                                                              for _ in range(15)]))
+            blk.append(min(((k, v) for k, v in times.items() if k[1] == 0), key=lambda kv: kv[1])[0][0])
+            b, g = min(times, key=times.get)
+            blk_g.append(b)
+            sgrid_g.append(g)
+    print(f"{w.name}: solo blocks {blk}; with grids {blk_g} {sgrid_g}", file=log, flush=True)
+    tune = cfg_g = None
     if cfg_arg:
-        sw, b, c = (int(v) for v in cfg_arg.split(","))
-        cfg = H.hf_config(sw, b, c, 0)
+        vals = [int(v) for v in cfg_arg.split(",")]
+        cfg = H.hf_config(vals[0], vals[1], vals[2], vals[3] if len(vals) == 4 else 0)
     else:
         cfg, tune = H.hf_tune(pr, H.HF_TUNE_EXHAUSTIVE)
         cfg = H.hf_config(cfg.split_waves, cfg.block, cfg.vgpr_cap, 0)
-    print(f"{w.name}: fused config {cfg}", file=log, flush=True)
+        cfg_g, _ = H.hf_tune(pr, H.HF_TUNE_EXHAUSTIVE_GRID)
+        cfg_g = H.hf_config(cfg_g.split_waves, cfg_g.block, cfg_g.vgpr_cap, cfg_g.grid)
+    print(f"{w.name}: fused config {cfg}; with the grid {cfg_g}", file=log, flush=True)
     regcap = None
     if tune is not None:
         # the register bound's effect (the paper's RegCap vs N-RegCap rows):
-        # the best unbounded and the best bounded candidate of the search
+        # the best unbounded and the best bounded candidate of the (split,
+        # block, cap) space at the default grid
         cands = H.hf_tune_candidates(H.HF_TUNE_EXHAUSTIVE, 0)
         prof = [(H.hf_profile(pr, c, 10), c) for c in cands]
         regcap = {}
@@ -284,7 +303,8 @@ def measure(w, cfg_arg, blocks_arg, steps, warmup, log=sys.stderr, cold=True):
         H.hf_run_fused_cfg(pr, cfg, stream)
 
     def run_serial():
-        H.hf_run_unfused(pr, blk[0], blk[1], H.HF_SERIAL, stream)
+        H.hf_run_solo(w.ta, blk[0], sgrid[0], stream)
+        H.hf_run_solo(w.tb, blk[1], sgrid[1], stream)
 
     def run_streams():
         H.hf_run_unfused(pr, blk[0], blk[1], H.HF_STREAMS, stream)
@@ -321,6 +341,28 @@ def measure(w, cfg_arg, blocks_arg, steps, warmup, log=sys.stderr, cold=True):
     print(f"{w.name}: fused {fused_ms:.4f} ms/step", file=log, flush=True)
     serial_ms, _ = timed(run_serial)
     streams_ms, _ = timed(run_streams)
+    grid_tuned = None
+    if cfg_g is not None and blk_g is not None:
+        def run_fused_g():
+            H.hf_run_fused_cfg(pr, cfg_g, stream)
+
+        def run_serial_g():
+            H.hf_run_solo(w.ta, blk_g[0], sgrid_g[0], stream)
+            H.hf_run_solo(w.tb, blk_g[1], sgrid_g[1], stream)
+
+        fg, fg_per = timed(run_fused_g)
+        sg, _ = timed(run_serial_g)
+        run_fused_g()
+        torch.cuda.synchronize()
+        g_out = [o.clone() for o in w.outs]
+        run_serial_g()
+        torch.cuda.synchronize()
+        grid_tuned = {"fused_ms": round(fg, 5), "serial_ms": round(sg, 5),
+                      "speedup_pct": round((sg / fg - 1.0) * 100.0, 3),
+                      "fused_kernel_ms": round(float(np.mean(fg_per)), 5),
+                      "config": [cfg_g.split_waves, cfg_g.block, cfg_g.vgpr_cap, cfg_g.grid],
+                      "solo_blocks": blk_g, "solo_grids": sgrid_g,
+                      "bit_exact": all(torch.equal(p, q) for p, q in zip(g_out, w.outs))}
     if cold:
         cold_reps = max(5, min(steps, 20))
         cold = {"fused_ms": timed_cold(run_fused, cold_reps), "serial_ms": timed_cold(run_serial, cold_reps),
@@ -329,8 +371,8 @@ def measure(w, cfg_arg, blocks_arg, steps, warmup, log=sys.stderr, cold=True):
         cold["fused_ms"], cold["serial_ms"] = round(cold["fused_ms"], 5), round(cold["serial_ms"], 5)
     else:
         cold = None
-    solo_ms = [float(np.median([H.hf_run_solo(t, b, timed=True) for _ in range(21)]))
-               for t, b in zip((w.ta, w.tb), blk)]
+    solo_ms = [float(np.median([H.hf_run_solo(t, b, g, timed=True) for _ in range(21)]))
+               for t, b, g in zip((w.ta, w.tb), blk, sgrid)]
     # the timed configuration reproduces the back-to-back result bit for bit
     run_fused()
     torch.cuda.synchronize()
@@ -338,7 +380,8 @@ def measure(w, cfg_arg, blocks_arg, steps, warmup, log=sys.stderr, cold=True):
     run_serial()
     torch.cuda.synchronize()
     bit_exact = all(torch.equal(p, q) for p, q in zip(f_out, w.outs))
-    return {"cfg": cfg, "tune": tune, "blk": blk, "fused_ms": fused_ms, "fused_per": fused_per,
+    return {"cfg": cfg, "tune": tune, "blk": blk, "sgrid": sgrid, "grid_tuned": grid_tuned,
+            "fused_ms": fused_ms, "fused_per": fused_per,
             "serial_ms": serial_ms, "streams_ms": streams_ms, "solo_ms": solo_ms, "bit_exact": bit_exact,
             "cold": cold, "regcap": regcap}
 
@@ -379,7 +422,7 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": w.desc,
-            "split_waves": cfg.split_waves, "block": cfg.block, "vgpr_cap": cfg.vgpr_cap,
+            "split_waves": cfg.split_waves, "block": cfg.block, "vgpr_cap": cfg.vgpr_cap, "grid": cfg.grid,
             "solo_blocks": m["blk"],
             "cache": "warm (no scrub between steps); cold_cache: 1 GiB scrub before every step",
         },
@@ -396,6 +439,7 @@ def main():
         "fused_step_ms_p10_p50_p90": [round(float(np.percentile(m["fused_per"], q)), 5) for q in (10, 50, 90)],
         "cold_cache": m["cold"],
         "register_bound": m["regcap"],
+        "grid_tuned": m["grid_tuned"],
         "fused_bit_exact_vs_serial": m["bit_exact"],
     }
     key = "fused_" + w.name.replace("+", "_")
@@ -421,19 +465,19 @@ def main():
         res["other_pairs"] = {}
         for name in WORKLOADS[1:]:
             o = Workload(name)
-            mo = measure(o, "", "", a.steps, 2, cold=not a.no_cold)
+            mo = measure(o, "", "", a.steps, a.warmup, cold=not a.no_cold)
             res["other_pairs"][name] = {
                 "fused_ms": round(mo["fused_ms"], 5), "serial_ms": round(mo["serial_ms"], 5),
                 "streams_ms": round(mo["streams_ms"], 5),
                 "speedup_pct": round((mo["serial_ms"] / mo["fused_ms"] - 1) * 100, 2),
                 "speedup_vs_streams_pct": round((mo["streams_ms"] / mo["fused_ms"] - 1) * 100, 2),
-                "config": [mo["cfg"].split_waves, mo["cfg"].block, mo["cfg"].vgpr_cap],
+                "config": [mo["cfg"].split_waves, mo["cfg"].block, mo["cfg"].vgpr_cap, mo["cfg"].grid],
                 "solo_blocks": mo["blk"], "bit_exact": mo["bit_exact"],
                 "hbm_gbps": round(o.alg_bytes / (float(np.mean(mo["fused_per"])) * 1e-3) / 1e9, 1),
                 "valu_busy": valu_busy_from_profiles("fused_" + name.replace("+", "_")),
                 "valu_busy_back_to_back": valu_busy_from_profiles("fused_" + name.replace("+", "_"), native=True),
                 "traffic": traffic_from_profiles("fused_" + name.replace("+", "_")),
-                "cold_cache": mo["cold"], "register_bound": mo["regcap"]}
+                "cold_cache": mo["cold"], "register_bound": mo["regcap"], "grid_tuned": mo["grid_tuned"]}
             del o
             torch.cuda.empty_cache()
     print(json.dumps(res), flush=True)

@@ -221,8 +221,17 @@ enum {
   HF_TUNE_PAPER = 1,      /* Main search of Sec. III-B: d0 = 1024, d1 = 128, 256, ..., 896; each
                              partition profiled without and with the bound r0       */
   HF_TUNE_NAIVE = 2,      /* even split, no bound, no search (Sec. IV-A "Naive")     */
-  HF_TUNE_MLP = 3         /* learned cost model ranks all candidates; only the top-k
+  HF_TUNE_MLP = 3,        /* learned cost model ranks all candidates; only the top-k
                              are profiled                                           */
+  HF_TUNE_EXHAUSTIVE_GRID = 4 /* EXHAUSTIVE, then the launch grid: the three best
+                             configurations profiled again at 2, 4 and 8 times the
+                             occupancy grid (skipped for a configuration whose
+                             default grid is below the occupancy grid).  Beyond the
+                             paper, whose fused grid follows the original kernels':
+                             every body here is a grid-stride loop, so the grid is
+                             free, and a grid larger than the resident workgroups
+                             lets a workgroup whose partitions finish at different
+                             times leave its CU to the next one                     */
 };
 typedef struct {
   int32_t n_candidates;   /* candidates the method considered                        */
@@ -236,7 +245,8 @@ typedef struct {
  * profiled candidate is launched `HF_TUNE_REPS` (default 20) times after a warm-up
  * launch; its time is the median.  The choice is the minimum median with the
  * first-found candidate winning ties (the strict comparison of that search).
- * `block` restricts EXHAUSTIVE/MLP to one block size (0 = 256, 512 and 1024).
+ * `block` restricts EXHAUSTIVE/EXHAUSTIVE_GRID/MLP to one block size (0 = 256,
+ * 512 and 1024).  Only EXHAUSTIVE_GRID returns a nonzero `grid`.
  * Outputs of the pair's tasks are overwritten by the profiling launches. */
 int hf_tune(const hf_pair* pr, int method, int block, int topk, void* stream,
             hf_config* best, hf_tune_stats* stats);

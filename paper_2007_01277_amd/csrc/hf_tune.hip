@@ -5,7 +5,11 @@
 // and keeps a candidate only when it is strictly faster.  The exhaustive mode
 // widens the space to workgroup sizes 256/512/1024, splits in eighths of the
 // workgroup (wavefront aligned) and every compiled VGPR bound.  The learned
-// mode ranks that space with the cost model and profiles only the top k.
+// mode ranks that space with the cost model and profiles only the top k.  The
+// grid mode adds the launch grid, a free parameter here because every body is a
+// grid-stride loop: the three best configurations of the exhaustive space are
+// profiled again at 2, 4 and 8 times the occupancy grid, which lets workgroups
+// whose partitions finish early leave the CU to new ones.
 #include <algorithm>
 #include <chrono>
 #include <cstdlib>
@@ -57,6 +61,7 @@ int candidates(int method, int block, int va, int vb, int lds, std::vector<hf_co
       return HF_OK;
     }
     case HF_TUNE_EXHAUSTIVE:
+    case HF_TUNE_EXHAUSTIVE_GRID:
     case HF_TUNE_MLP: {
       const int blocks[] = {256, 512, 1024};
       for (int b : blocks) {
@@ -143,7 +148,7 @@ int hf_profile(const hf_pair* pr, const hf_config* cfg, int reps, void* stream, 
 int hf_tune(const hf_pair* pr, int method, int block, int topk, void* stream, hf_config* best,
             hf_tune_stats* stats) {
   if (!pr || !best) return HF_EINVAL;
-  if (method < HF_TUNE_EXHAUSTIVE || method > HF_TUNE_MLP) return HF_EINVAL;
+  if (method < HF_TUNE_EXHAUSTIVE || method > HF_TUNE_EXHAUSTIVE_GRID) return HF_EINVAL;
   int rc;
   if ((rc = validate_task(&pr->a)) != HF_OK || (rc = validate_task(&pr->b)) != HF_OK) return rc;
   if (block != 0 && check_block(block) != HF_OK) return HF_EINVAL;
@@ -174,9 +179,11 @@ int hf_tune(const hf_pair* pr, int method, int block, int topk, void* stream, hf
 
   float tbest = 0.f;
   int ibest = -1, nprof = 0;
+  std::vector<float> times(cands.size(), 0.f);
   for (int i : order) {
     float t = 0.f;
     if ((rc = profile(s, pr, cands[i], reps, st, &t)) != HF_OK) return rc;
+    times[i] = t;
     ++nprof;
     if (ibest < 0 || t < tbest) {  // strict: the first-found candidate keeps ties
       tbest = t;
@@ -184,9 +191,34 @@ int hf_tune(const hf_pair* pr, int method, int block, int topk, void* stream, hf
     }
   }
   *best = cands[ibest];
+  int ncand = (int)cands.size();
+  if (method == HF_TUNE_EXHAUSTIVE_GRID) {
+    std::vector<int> top(order);
+    std::stable_sort(top.begin(), top.end(), [&](int x, int y) { return times[x] < times[y]; });
+    if (top.size() > 3) top.resize(3);
+    for (int i : top) {
+      hf_config c = cands[i];
+      hf_kernel_info fi;
+      if ((rc = hf_fused_info(pr->a.kind, pr->b.kind, c.block, c.vgpr_cap, &fi)) != HF_OK) return rc;
+      int used = 0;
+      if ((rc = launch_fused(s, pr, &c, st, &used)) != HF_OK) return rc;
+      if (used < fi.default_grid) continue;  // too little work to fill even the occupancy grid
+      for (int m : {2, 4, 8}) {
+        c.grid = fi.default_grid * m;
+        float t = 0.f;
+        if ((rc = profile(s, pr, c, reps, st, &t)) != HF_OK) return rc;
+        ++nprof;
+        ++ncand;
+        if (t < tbest) {
+          tbest = t;
+          *best = c;
+        }
+      }
+    }
+  }
   if (stats) {
     std::memset(stats, 0, sizeof(*stats));
-    stats->n_candidates = (int)cands.size();
+    stats->n_candidates = ncand;
     stats->n_profiled = nprof;
     stats->t_best_ms = tbest;
     stats->reps = reps;

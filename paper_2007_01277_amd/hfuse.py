@@ -18,7 +18,7 @@ HF_OK, HF_EINVAL, HF_EUNSUPPORTED, HF_EHIP, HF_ETIMEOUT, HF_ENOMEM, HF_ENOMODEL 
  HF_ETHASH) = range(9)
 KIND_NAMES = ["bn_stats", "int_mix", "im2col", "lds_hist", "upsample", "maxpool", "sha256d", "blake2b", "ethash"]
 HF_SERIAL, HF_STREAMS = 0, 1
-HF_TUNE_EXHAUSTIVE, HF_TUNE_PAPER, HF_TUNE_NAIVE, HF_TUNE_MLP = range(4)
+HF_TUNE_EXHAUSTIVE, HF_TUNE_PAPER, HF_TUNE_NAIVE, HF_TUNE_MLP, HF_TUNE_EXHAUSTIVE_GRID = range(5)
 CAPS = (0, 64, 80, 96, 128)
 
 

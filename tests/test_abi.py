@@ -215,6 +215,7 @@ def test_run_entry_points_reject_before_touching_the_gpu():
     assert L.hf_run_vfused(ctypes.byref(pr), 384, 0, None, None) == H.HF_EINVAL
     assert L.hf_run_vfused(None, 256, 0, None, None) == H.HF_EINVAL
     assert L.hf_tune(ctypes.byref(pr), 9, 0, 3, None, ctypes.byref(H.hf_config()), None) == H.HF_EINVAL
+    assert L.hf_tune(ctypes.byref(pr), 5, 0, 3, None, ctypes.byref(H.hf_config()), None) == H.HF_EINVAL
 
 
 @pytest.mark.parametrize("d1,d2,va,vb,lds", [(896, 128, 32, 32, 1024), (512, 512, 63, 11, 12),
@@ -240,6 +241,10 @@ def test_exhaustive_candidates_are_wave_aligned_eighths():
         [(1024, 2 * k) for k in range(1, 8)]
     assert len(c) == 17 * len(H.CAPS)
     assert H.hf_tune_candidates(H.HF_TUNE_NAIVE, 0)[0].as_tuple() == (8, 1024, 0, 0)
+    # the grid mode starts from the same space; its grid stage runs on the GPU
+    g = H.hf_tune_candidates(H.HF_TUNE_EXHAUSTIVE_GRID, 0)
+    assert [x.as_tuple() for x in g] == [x.as_tuple() for x in c]
+    assert all(x.grid == 0 for x in g)
 
 
 def test_batch_create_rejects_bad_groups_before_the_gpu():

@@ -122,6 +122,27 @@ def test_repeated_launches_leave_scratch_clean():
             assert torch.equal(x, y)
 
 
+@pytest.mark.parametrize("method", [H.HF_TUNE_EXHAUSTIVE, H.HF_TUNE_PAPER, H.HF_TUNE_NAIVE,
+                                    H.HF_TUNE_EXHAUSTIVE_GRID], ids=["exhaustive", "paper", "naive", "grid"])
+def test_tuned_configuration_matches_oracle(method):
+    """Every search returns a legal configuration whose fused run matches the
+    oracle; the grid mode's grid is 0 or 2, 4 or 8 times the occupancy grid."""
+    ca = G.bn_case((16, 64, 32, 32), seed=8)
+    cb = G.mix_case(1 << 22, 8, seed=8, sample=4096)
+    pr = H.make_pair(ca.task, cb.task)
+    best, st = H.hf_tune(pr, method)
+    print(method, best, st, flush=True)
+    assert H.hf_validate_fused(pr, best) == H.HF_OK
+    assert st["n_profiled"] >= 1 and st["t_best_ms"] > 0
+    if method == H.HF_TUNE_EXHAUSTIVE_GRID:
+        assert 85 <= st["n_candidates"] <= 85 + 9
+        occ = H.hf_fused_info(ca.task.kind, cb.task.kind, best.block, best.vgpr_cap)["default_grid"]
+        assert best.grid in (0, 2 * occ, 4 * occ, 8 * occ)
+    else:
+        assert best.grid == 0
+    G.run_and_check(lambda: H.hf_run_fused_cfg(pr, best), [ca, cb])
+
+
 def test_fused_grid_independent():
     ca = G.bn_case((4, 8, 30, 28), seed=6)
     cb = G.hist_case(777_777, seed=6)
