@@ -96,9 +96,29 @@ def stats(a):
         out += ["", f"Dispatches {skip + 1}..{skip + k} of `{short(a.timed_match)}` in the per-dispatch trace "
                 f"(the {k} timed steps after {skip} warmup steps): avg {statistics.fmean(d):.2f} us, median {statistics.median(d):.2f} us, min {min(d):.2f} us, "
                 f"max {max(d):.2f} us."]
+    for m in (a.alone or []):
+        for grid, (n, avg, lo) in sorted(alone_by_grid_us(a.trace, m).items()):
+            out += ["", f"`{short(m)}` at grid {grid} lanes, dispatches that ran alone: {n}, "
+                        f"avg {avg:.2f} us, min {lo:.2f} us."]
     if a.note:
         out += ["", a.note]
     open(a.out, "w").write("\n".join(out) + "\n")
+
+
+def alone_by_grid_us(trace_csv, match):
+    """{grid lanes: (count, avg us, min us)} over the dispatches of `match` that
+    overlap no other dispatch, from a --kernel-trace per-dispatch CSV."""
+    rows = [(int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"], int(r["Grid_Size_X"]))
+            for r in csv.DictReader(open(trace_csv))]
+    rows.sort()
+    res, end_max = {}, None
+    for i, (s, e, name, g) in enumerate(rows):
+        before = end_max is not None and end_max > s
+        after = i + 1 < len(rows) and rows[i + 1][0] < e
+        end_max = e if end_max is None else max(end_max, e)
+        if match in name and not (before or after):
+            res.setdefault(g, []).append((e - s) / 1e3)
+    return {g: (len(v), sum(v) / len(v), min(v)) for g, v in res.items()}
 
 
 def launches_us(trace_csv, match, skip, k):
@@ -234,6 +254,7 @@ def main():
     s.add_argument("--trace", default="", help="the per-dispatch kernel trace CSV of the same run")
     s.add_argument("--timed", default="", help="W,K: also summarise dispatches W+1..W+K of --timed-match")
     s.add_argument("--timed-match", default="")
+    s.add_argument("--alone", action="append", help="per-grid averages of this kernel's dispatches that ran alone")
     for p in (s,):
         p.add_argument("--cmd", required=True)
         p.add_argument("--out", required=True)

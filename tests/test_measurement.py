@@ -52,3 +52,12 @@ def test_alone_average_leaves_out_concurrent_launches(tmp_path):
     assert RS.alone_avg_ns(str(f), "B") == 4.0
     with pytest.raises(SystemExit):
         RS.alone_avg_ns(str(f), "C")
+
+
+def test_alone_by_grid_groups_dispatches_by_grid(tmp_path):
+    rows = [("K", 0, 10, 64), ("K", 20, 50, 128), ("J", 40, 60, 64), ("K", 70, 80, 64), ("K", 90, 96, 128)]
+    f = tmp_path / "trace.csv"
+    f.write_text("Kernel_Name,Start_Timestamp,End_Timestamp,Grid_Size_X\n" +
+                 "".join(f"{n},{s},{e},{g}\n" for n, s, e, g in rows))
+    res = RS.alone_by_grid_us(str(f), "K")
+    assert res == {64: (2, 0.01, 0.01), 128: (1, 0.006, 0.006)}
