@@ -455,6 +455,10 @@ def main():
                            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                            "traffic": traffic_from_profiles(key), "kernel": w.kernel,
                            "kernel_ms": round(kernel_ms, 5)}
+    if m["grid_tuned"]:
+        gk = m["grid_tuned"]["fused_kernel_ms"] * 1e-3
+        m["grid_tuned"]["roofline_frac"] = round(
+            (w.alg_ops / gk / 1e12 / INT_PEAK_TOPS) if w.bound == "alu" else (w.alg_bytes / gk / 1e9 / HBM_PEAK_GBS), 4)
     if m["tune"]:
         res["tune"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in m["tune"].items()}
     if not a.no_cpu:
