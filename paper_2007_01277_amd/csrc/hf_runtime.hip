@@ -585,6 +585,10 @@ int kernel_info(DeviceState* s, const void* fn, int block, hf_kernel_info* out) 
 }
 
 // ------------------------------------------------------------------ microbenchmarks
+// Copies n float4.  Launched with one element per lane: a lane that loops over
+// several elements waits, at each load, for its previous store as well (the
+// vector-memory counter retires in order), which costs about a fifth of the
+// copy rate; a lane that exits after its store does not wait for it.
 __global__ void __launch_bounds__(256) k_copy(float4* __restrict__ dst, const float4* __restrict__ src,
                                               uint64_t n) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -826,7 +830,7 @@ int hf_copy(void* dst, const void* src, int64_t bytes, void* stream, float* ms_o
   hipStream_t st = static_cast<hipStream_t>(stream);
   if ((rc = timed_begin(s, st, ms_out)) != HF_OK) return rc;
   const uint64_t n = (uint64_t)bytes / 16;
-  const int grid = std::max(1, std::min<int>((int)((n + 255) / 256), s->num_cus * 8));
+  const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>((n + 255) / 256, uint64_t(1) << 30));
   hipLaunchKernelGGL(k_copy, dim3(grid), dim3(256), 0, st, static_cast<float4*>(dst),
                      static_cast<const float4*>(src), n);
   hipError_t e = hipGetLastError();
