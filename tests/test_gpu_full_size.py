@@ -94,3 +94,39 @@ def test_ethash_sha256d_full_size():
         outs = _fused_vs_serial(ca, cb, cfg)
     ca.check(outs[:1])
     cb.check(outs[1:])
+
+
+def test_largest_element_counts_int_mix_and_hist():
+    """The largest counts the ABI accepts (2^31 - 1 elements per buffer, odd, so
+    both bodies take their ragged tails): int_mix over 2^31 - 1 words fused with
+    a histogram of 2^31 - 1 bytes, against the oracle (sampled words, every
+    count) and against the back-to-back run."""
+    from paper_2007_01277_amd import inputs
+    import oracle
+    n = (1 << 31) - 1
+    seeds = inputs.cuda_uint32(n, 41)
+    mixed = torch.empty_like(seeds)
+    data = torch.empty(n, dtype=torch.uint8, device="cuda")
+    chunk = 1 << 28
+    for k, s in enumerate(range(0, n, chunk)):
+        e = min(n, s + chunk)
+        data[s:e] = inputs.cuda_zipf_u8(e - s, 42 + k)
+    counts = torch.empty(256, dtype=torch.int32, device="cuda")
+    ta, tb = H.task_int_mix(seeds, mixed, 2), H.task_lds_hist(data, counts)
+    pr = H.make_pair(ta, tb)
+    print("int_mix 2^31-1 x 2 rounds + lds_hist 2^31-1 bytes", flush=True)
+    H.hf_run_unfused(pr, 1024, 1024, H.HF_SERIAL)
+    torch.cuda.synchronize()
+    ref_mixed, ref_counts = mixed.clone(), counts.clone()
+    mixed.zero_()
+    counts.zero_()
+    H.hf_run_fused_cfg(pr, H.hf_config(8, 1024, 0, 0))
+    torch.cuda.synchronize()
+    assert torch.equal(mixed, ref_mixed) and torch.equal(counts, ref_counts)
+    idx = np.unique(np.concatenate([np.arange(64), np.arange(n - 64, n),
+                                    inputs.rng(43).integers(0, n, size=4096)]))
+    it = torch.from_numpy(idx).cuda()
+    want = oracle.int_mix(seeds[it].cpu().numpy().view(np.uint32), 2)
+    assert np.array_equal(mixed[it].cpu().numpy().view(np.uint32), want)
+    host = data.cpu().numpy()
+    assert np.array_equal(counts.cpu().numpy().astype(np.uint64), oracle.hist256(host))
