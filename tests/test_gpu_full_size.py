@@ -130,3 +130,32 @@ def test_largest_element_counts_int_mix_and_hist():
     assert np.array_equal(mixed[it].cpu().numpy().view(np.uint32), want)
     host = data.cpu().numpy()
     assert np.array_equal(counts.cpu().numpy().astype(np.uint64), oracle.hist256(host))
+
+
+def test_largest_channel_bn_stats():
+    """One channel of 2^31 - 1 - 2^20 elements (a ragged last unit; the ABI's
+    limit is 2^31 - 1 per buffer), solo and fused with a small int_mix, against
+    the oracle's two-pass double statistics."""
+    from paper_2007_01277_amd import inputs
+    import oracle
+    from tests.gpu_cases import TOL
+    shape = (1, 1, 1, (1 << 31) - 1 - (1 << 20))
+    x = inputs.cuda_normal(shape, 44)
+    x.mul_(2.0).add_(1.0)
+    mean = torch.full((1,), 7.0, device="cuda")
+    var = torch.full((1,), 7.0, device="cuda")
+    ta = H.task_bn_stats(x, mean, var)
+    cb = G.mix_case(100_003, 3, seed=44)
+    print("bn_stats one channel of", shape[3], "elements", flush=True)
+    m_ref, v_ref = oracle.bn_stats(x.cpu().numpy())
+    for run in (lambda: H.hf_run_solo(ta, 1024), lambda: H.hf_run_fused_cfg(H.make_pair(ta, cb.task),
+                                                                             H.hf_config(8, 1024, 0, 0))):
+        mean.fill_(7.0)
+        var.fill_(7.0)
+        cb.reset()
+        run()
+        torch.cuda.synchronize()
+        m, v = float(mean.item()), float(var.item())
+        assert abs(m - m_ref[0]) <= TOL * (abs(m_ref[0]) + np.sqrt(v_ref[0])), (m, m_ref)
+        assert abs(v - v_ref[0]) <= TOL * v_ref[0], (v, v_ref)
+    cb.check(cb.outputs())
