@@ -390,7 +390,7 @@ def main():
     a = parse()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {a.gpus}); the fused kernel's "
-              "multi-GPU sharding is described in DESIGN.md and not run", file=sys.stderr)
+              "sharding over several GPUs is designed but not run", file=sys.stderr)
         return 2
     import numpy as np
     import torch

@@ -36,7 +36,7 @@ nonce0 + i (mod 2^32); each instance outputs a 32-byte digest.
     Pins: the FNV step against the published FNV-1 test values, the all-zero
     table closed form of the 64 folds and the final 4-to-1 fold, and which rows
     the computation depends on.  The seed chain (h, s) and the row index
-    formula are this build's definition with no independent pin ("parity
+    formula are this library's own definition with no independent pin ("parity
     unpinned" for those two steps).
 """
 from __future__ import annotations

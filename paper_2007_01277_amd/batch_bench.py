@@ -17,7 +17,7 @@ Modes timed (median of `reps` runs, events on the launch stream):
   batch          the persistent N-way fused kernel, one launch
   batch_graph    the same launch replayed from a captured HIP graph
 
-    python -m paper_2007_01277_amd.batch_bench --count 1000 --out gpurun_out/batch.json
+    python -m paper_2007_01277_amd.batch_bench --count 1000 --out batch.json
 """
 from __future__ import annotations
 

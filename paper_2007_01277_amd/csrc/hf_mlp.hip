@@ -7,7 +7,7 @@
 // two backward products, Adam), all deterministic: every output element is
 // written by one lane that reduces in a fixed order, with no atomics.  The
 // tuner ranks every candidate with it and profiles only the best k; the
-// exhaustive search remains the fallback and the judge of its regret.
+// exhaustive search remains the fallback and the reference for its regret.
 //
 // Parameter layout (one flat fp32 vector): W1[d][64] b1[64] W2[64][64] b2[64]
 // W3[64][64] b3[64] W4[64][1] b4[1], row-major W[in][out].

@@ -11,7 +11,7 @@ features.  Cross-validation is by pair: the model is trained on a random subset
 of ``per_pair`` configurations of each training pair (600 pairs x 14 = about
 6300 training samples per fold at the defaults: the sample budget is spread
 over many pairs, which generalises far better than many configurations of few
-pairs) and judged on the held-out pairs, where it ranks all candidates and
+pairs) and evaluated on the held-out pairs, where it ranks all candidates and
 only the top k are "profiled" (their measured times are looked up).
 Regret = T(choice) / T(exhaustive best) - 1.
 
@@ -19,7 +19,7 @@ Baselines without the network: the even split at block 1024 without a bound
 ("naive", Sec. IV-A), the even split with the register bound r0 of Sec. III-B
 ("r0"), and k candidates drawn at random.
 
-    python -m paper_2007_01277_amd.learned_tuner --pairs 40 --out gpurun_out/tuner.json
+    python -m paper_2007_01277_amd.learned_tuner --pairs 40 --out tuner.json
 """
 from __future__ import annotations
 

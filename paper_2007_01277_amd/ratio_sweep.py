@@ -26,7 +26,7 @@ vertical fusion at its best block; Streams = the two kernels on two streams;
 Serial = back to back.  Speedup % = (T_serial / T_method - 1) * 100; the ratio
 is t_star / t_other of the best solo times.
 
-    python -m paper_2007_01277_amd.ratio_sweep --out gpurun_out/ratio.json
+    python -m paper_2007_01277_amd.ratio_sweep --out ratio.json
 
 ``--sets`` picks the groups: ``data`` (the first five pairs), ``crypto`` (the
 three hash pairs), ``paper`` (both) and ``memmem``.
