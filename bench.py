@@ -262,7 +262,7 @@ def measure(w, cfg_arg, blocks_arg, steps, warmup, log=sys.stderr, cold=True):
         # (the headline protocol) and, for the grid-tuned comparison, at its best
         # (workgroup size, grid) with the grid 2, 4 or 8 times the occupancy grid
         # (each candidate timed over back-to-back launches, as the timed steps run)
-        def solo_ms(t, b, g, n=10):
+        def solo_ms(t, b, g, n=20):
             for _ in range(3):
                 H.hf_run_solo(t, b, g, stream)
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -276,10 +276,12 @@ def measure(w, cfg_arg, blocks_arg, steps, warmup, log=sys.stderr, cold=True):
         blk, sgrid, blk_g, sgrid_g = [], [0, 0], [], []
         for t in (w.ta, w.tb):
             times = {}
-            for b in (256, 512, 1024):
-                occ = H.hf_solo_info(t.kind, b)["default_grid"]
-                for mult in (0, 2, 4, 8):
-                    times[(b, occ * mult)] = solo_ms(t, b, occ * mult)
+            for _ in range(2):  # two passes over the candidates; each keeps its faster pass
+                for b in (256, 512, 1024):
+                    occ = H.hf_solo_info(t.kind, b)["default_grid"]
+                    for mult in (0, 2, 4, 8):
+                        ms = solo_ms(t, b, occ * mult)
+                        times[(b, occ * mult)] = min(ms, times.get((b, occ * mult), ms))
             blk.append(min(((k, v) for k, v in times.items() if k[1] == 0), key=lambda kv: kv[1])[0][0])
             b, g = min(times, key=times.get)
             blk_g.append(b)
