@@ -165,6 +165,22 @@ def crypto(res, reps):
         res[name] = rows
 
 
+SETS = ("data", "crypto", "memmem")
+
+
+def parse_sets(spec: str) -> set:
+    """The groups named by ``--sets``: ``paper`` stands for data and crypto."""
+    out = set()
+    for s in (x.strip() for x in spec.split(",") if x.strip()):
+        if s == "paper":
+            out |= {"data", "crypto"}
+        elif s in SETS:
+            out.add(s)
+        else:
+            raise SystemExit(f"unknown set {s!r}: choose from paper, {', '.join(SETS)}")
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--reps", type=int, default=15)
@@ -177,9 +193,7 @@ def main(argv=None):
     H.hf_init()
     H.hf_warmup(300)
     res = {}
-    sets = a.sets.split(",")
-    if "paper" in sets:
-        sets += ["data", "crypto"]
+    sets = parse_sets(a.sets)
     if "memmem" in sets:
         memmem(res, a.reps)
     if "data" not in sets:

@@ -40,3 +40,13 @@ def test_alu_roofline_constants():
     assert abs(bench.INT_PEAK_TOPS - 39.3216) < 1e-9
     assert bench.OPS_PER_ROUND == 8
     assert bench.HBM_PEAK_GBS == 8000
+
+
+def test_ratio_sweep_sets():
+    from paper_2007_01277_amd import ratio_sweep as RSW
+    assert RSW.parse_sets("paper,memmem") == {"data", "crypto", "memmem"}
+    assert RSW.parse_sets("crypto") == {"crypto"}
+    assert RSW.parse_sets("data, memmem") == {"data", "memmem"}
+    import pytest
+    with pytest.raises(SystemExit):
+        RSW.parse_sets("hashes")
