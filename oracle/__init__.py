@@ -5,9 +5,10 @@ Only the test suite, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 (``paper_2007_01277_amd``) and never imports it.
 
 The arithmetic lives in ``hf_oracle.c`` (plain loops, double accumulation);
-this module only compiles it with gcc, loads it with ctypes and converts numpy
-arrays.  The register-bound rule and the learned cost model's reference maths
-are in ``search.py`` and ``mlp.py`` of this package.
+this module only compiles it with gcc (a sequential and an OpenMP build of the
+same source), loads it with ctypes and converts numpy arrays.  The
+register-bound rule and the learned cost model's reference maths are in
+``search.py`` and ``mlp.py`` of this package.
 """
 from __future__ import annotations
 
@@ -20,29 +21,48 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "hf_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
-_lib = None
+_LIB_OMP = os.path.join(_HERE, "liboracle_omp.so")
+_libs = {}
+_use_omp = False
 
 
 def build(force: bool = True) -> str:
-    """Compile hf_oracle.c into liboracle.so with gcc (-O2, no fast-math)."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
-        subprocess.check_call(
-            ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
-             "-fvisibility=hidden", _SRC, "-o", tmp, "-lm"])
-        os.replace(tmp, _LIB)
+    """Compile hf_oracle.c with gcc (-O2, no fast-math) twice: liboracle.so,
+    sequential, and liboracle_omp.so, the same source with OpenMP."""
+    for lib, extra in ((_LIB, []), (_LIB_OMP, ["-fopenmp"])):
+        if force or not os.path.exists(lib):
+            tmp = lib + ".tmp"
+            subprocess.check_call(
+                ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
+                 "-fvisibility=hidden"] + extra + [_SRC, "-o", tmp, "-lm"])
+            os.replace(tmp, lib)
     return _LIB
 
 
+def use_openmp(on: bool) -> None:
+    """Route the oracle functions to the OpenMP build (True) or to the
+    sequential build (False, the default)."""
+    global _use_omp
+    _use_omp = bool(on)
+
+
+def threads() -> int:
+    """Threads the current build's parallel loops use (1 when sequential)."""
+    return int(_load().oracle_threads())
+
+
 def _load():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_LIB):
+    path = _LIB_OMP if _use_omp else _LIB
+    lib = _libs.get(path)
+    if lib is None:
+        if not os.path.exists(path):
             build(force=False)
-        lib = ctypes.CDLL(_LIB)
+        lib = ctypes.CDLL(path)
         P = ctypes.c_void_p
         I64 = ctypes.c_int64
         I32 = ctypes.c_int32
+        lib.oracle_threads.argtypes = []
+        lib.oracle_threads.restype = ctypes.c_int
         lib.oracle_bn_stats.argtypes = [P, I64, I64, I64, I64, P, P]
         lib.oracle_bn_stats.restype = ctypes.c_int
         lib.oracle_int_mix.argtypes = [P, I64, I32, P]
@@ -57,8 +77,10 @@ def _load():
         lib.oracle_upsample_absmag.restype = ctypes.c_int
         lib.oracle_maxpool.argtypes = [P, I64, I64, I64, I64, I32, I32, I32, I32, P, P]
         lib.oracle_maxpool.restype = ctypes.c_int
-        _lib = lib
-    return _lib
+        lib.oracle_ethash_like.argtypes = [P, ctypes.c_uint32, I64, P, I64, P]
+        lib.oracle_ethash_like.restype = ctypes.c_int
+        _libs[path] = lib
+    return lib
 
 
 def _ptr(a: np.ndarray) -> int:
@@ -147,3 +169,16 @@ def maxpool(x: np.ndarray, kh: int, kw: int, stride: int, pad: int):
     if rc != 0:
         raise ValueError("bad maxpool parameters")
     return out, idx
+
+
+def ethash_like(header: bytes, nonce0: int, table: np.ndarray, n: int) -> np.ndarray:
+    """Digests [n][32] (uint8) of the Ethash-like walk over `table` [rows][32]
+    uint32 (the C transcription of the definition in hashes.py)."""
+    hdr = np.frombuffer(bytes(header), np.uint8)
+    assert hdr.size == 80
+    table = np.ascontiguousarray(table, dtype=np.uint32)
+    out = np.empty((n, 32), np.uint8)
+    rc = _load().oracle_ethash_like(_ptr(hdr), nonce0 & 0xFFFFFFFF, n, _ptr(table), table.shape[0], _ptr(out))
+    if rc != 0:
+        raise ValueError("bad Ethash-like parameters")
+    return out

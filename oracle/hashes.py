@@ -26,18 +26,21 @@ nonce0 + i (mod 2^32); each instance outputs a 32-byte digest.
     of its inner loop: a 32-word mix is folded with 64 pseudo-random 128-byte
     table rows, the row of access i chosen from the mix, by the FNV step
     fnv(a, b) = (a * 16777619) ^ b (mod 2^32).  Definition used here:
-      m[0..18] = header words (little-endian u32), m[19] = nonce;
-      h = 2166136261; h = fnv(h, w) for w in m;
-      s[0] = h; s[k] = fnv(s[k-1], k) for k = 1..15;  mix[j] = s[j mod 16];
+      msg = the 80-byte message of the instance (header[0:76] || le32(nonce));
+      s[0] = FNV-1 (32 bits) of the 80 bytes of msg;
+      s[k] = fnv(s[k-1], k) for k = 1..15, i.e. s[k] is FNV-1 of msg followed
+             by the bytes 1, 2, ..., k;  mix[j] = s[j mod 16];
       for i in 0..63: p = fnv(i ^ s[0], mix[i mod 32]) mod R;
                       mix[j] = fnv(mix[j], T[p][j]) for j in 0..31;
       out[k] = fnv(fnv(fnv(mix[4k], mix[4k+1]), mix[4k+2]), mix[4k+3]), k < 8;
       digest = out[0..7] as little-endian bytes.
-    Pins: the FNV step against the published FNV-1 test values, the all-zero
-    table closed form of the 64 folds and the final 4-to-1 fold, and which rows
-    the computation depends on.  The seed chain (h, s) and the row index
-    formula are this library's own definition with no independent pin ("parity
-    unpinned" for those two steps).
+    The row of access i is Ethash's own access formula (its hashimoto loop)
+    with the table's row count in place of the dataset's page count.
+    Pins: the FNV step and the seed chain against the published FNV-1 test
+    values (s[k] is FNV-1 of a byte string), the all-zero-table closed form
+    of the 64 folds and of the final 4-to-1 fold, and which rows the
+    computation depends on.  The access formula itself is a stated reading
+    (Ethash's), checked only through those dependence tests.
 """
 from __future__ import annotations
 
@@ -231,10 +234,9 @@ def ethash_like_one(header: bytes, nonce: int, table, rows_accessed=None) -> byt
     sequence of R rows of 32 uint32 words; `rows_accessed`, if a list, receives
     the 64 row indices in access order."""
     R = len(table)
-    m = [int.from_bytes(header[4 * k: 4 * k + 4], "little") for k in range(19)] + [nonce & M32]
     h = FNV_OFFSET
-    for w in m:
-        h = fnv(h, w)
+    for byte in message(header, nonce):
+        h = fnv(h, byte)
     s = [h]
     for k in range(1, 16):
         s.append(fnv(s[k - 1], k))

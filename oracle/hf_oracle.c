@@ -37,13 +37,32 @@
  *
  * Parity pins (closed forms, published values, library routines, brute force)
  * live in the oracle tests; none of them calls back into this file's formulas.
+ *
+ * The file is compiled twice: sequentially (the oracle the tests use) and with
+ * OpenMP (-fopenmp), where the `omp` pragmas below spread independent units
+ * over the host's cores -- channels, elements, (image, channel) planes, and
+ * thread-private histograms summed at the end.  The arithmetic of every unit
+ * is the same in both builds, so both give the same results (bn_stats sums
+ * each channel in one thread, in the same order).
  */
 #include <math.h>
 #include <stddef.h>
 #include <stdint.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define OR_EXPORT __attribute__((visibility("default")))
+
+/* Threads the parallel loops use (1 in the sequential build). */
+OR_EXPORT int oracle_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
 
 /* ------------------------------------------------------------------ bn_stats */
 /* mean[c] = (1/M) sum_{n,h,w} x[n,c,h,w];  var[c] = (1/M) sum (x - mean[c])^2,
@@ -53,6 +72,7 @@ OR_EXPORT int oracle_bn_stats(const float* x, int64_t N, int64_t C, int64_t H,
   const int64_t HW = H * W;
   const int64_t M = N * HW;
   if (M <= 0) return -1;
+#pragma omp parallel for schedule(dynamic, 1)
   for (int64_t c = 0; c < C; ++c) {
     double s = 0.0;
     for (int64_t n = 0; n < N; ++n) {
@@ -77,6 +97,7 @@ OR_EXPORT int oracle_bn_stats(const float* x, int64_t N, int64_t C, int64_t H,
 /* ------------------------------------------------------------------ int_mix */
 OR_EXPORT void oracle_int_mix(const uint32_t* seed, int64_t n, int32_t rounds,
                               uint32_t* out) {
+#pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; ++i) {
     uint32_t x = seed[i];
     for (int32_t r = 0; r < rounds; ++r) {
@@ -93,6 +114,7 @@ OR_EXPORT void oracle_int_mix(const uint32_t* seed, int64_t n, int32_t rounds,
 /* counts[b] = number of i with in[i] == b, b in [0, 256). */
 OR_EXPORT void oracle_hist256(const uint8_t* in, int64_t n, uint64_t* counts) {
   for (int b = 0; b < 256; ++b) counts[b] = 0;
+#pragma omp parallel for schedule(static) reduction(+ : counts[:256])
   for (int64_t i = 0; i < n; ++i) counts[in[i]] += 1;
 }
 
@@ -107,6 +129,7 @@ OR_EXPORT int oracle_im2col(const float* x, int64_t N, int64_t C, int64_t H,
   const int64_t Wo = (W + 2 * p - kw) / s + 1;
   if (Ho <= 0 || Wo <= 0) return -1;
   const int64_t rows = C * kh * kw;
+#pragma omp parallel for collapse(2) schedule(static)
   for (int64_t n = 0; n < N; ++n)
     for (int64_t c = 0; c < C; ++c)
       for (int32_t i = 0; i < kh; ++i)
@@ -145,6 +168,7 @@ OR_EXPORT int oracle_upsample(const float* x, int64_t N, int64_t C, int64_t H,
                               int64_t W, int32_t s, double* out) {
   if (s <= 0 || H <= 0 || W <= 0) return -1;
   const int64_t Ho = H * s, Wo = W * s;
+#pragma omp parallel for collapse(2) schedule(static)
   for (int64_t n = 0; n < N; ++n)
     for (int64_t c = 0; c < C; ++c) {
       const float* img = x + (n * C + c) * H * W;
@@ -176,6 +200,7 @@ OR_EXPORT int oracle_upsample_absmag(const float* x, int64_t N, int64_t C,
                                      double* out) {
   if (s <= 0 || H <= 0 || W <= 0) return -1;
   const int64_t Ho = H * s, Wo = W * s;
+#pragma omp parallel for collapse(2) schedule(static)
   for (int64_t n = 0; n < N; ++n)
     for (int64_t c = 0; c < C; ++c) {
       const float* img = x + (n * C + c) * H * W;
@@ -208,6 +233,8 @@ OR_EXPORT int oracle_maxpool(const float* x, int64_t N, int64_t C, int64_t H, in
   if (kh < 1 || kw < 1 || s < 1 || p < 0 || p >= kh || p >= kw) return -1;
   if (H + 2 * p < kh || W + 2 * p < kw) return -1;
   const int64_t Ho = (H + 2 * p - kh) / s + 1, Wo = (W + 2 * p - kw) / s + 1;
+  int bad = 0;
+#pragma omp parallel for collapse(2) schedule(static) reduction(| : bad)
   for (int64_t n = 0; n < N; ++n)
     for (int64_t c = 0; c < C; ++c) {
       const float* img = x + (n * C + c) * H * W;
@@ -232,10 +259,48 @@ OR_EXPORT int oracle_maxpool(const float* x, int64_t N, int64_t C, int64_t H, in
               }
             }
           }
-          if (!have) return -1;
+          if (!have) bad = 1; /* a window with no in-range element */
           dst[oh * Wo + ow] = best;
           dix[oh * Wo + ow] = (int32_t)at;
         }
     }
+  return bad ? -1 : 0;
+}
+
+/* --------------------------------------------------------------- Ethash-like */
+/* The Ethash-like walk written out in C for the full-size checks; the same
+ * definition as oracle/hashes.py (the tests check the two against each other):
+ * msg = header[0:76] || le32(nonce0 + i);  s0 = FNV-1 of the 80 bytes of msg;
+ * s_k = fnv(s_(k-1), k);  mix_j = s_(j mod 16);  for a = 0..63:
+ * p = fnv(a ^ s0, mix_(a mod 32)) mod rows, mix_j = fnv(mix_j, T[p][j]);
+ * out_k = fnv(fnv(fnv(mix_4k, mix_4k+1), mix_4k+2), mix_4k+3), as 8
+ * little-endian words per instance. */
+static uint32_t fnv32(uint32_t a, uint32_t b) { return (a * 16777619u) ^ b; }
+
+OR_EXPORT int oracle_ethash_like(const uint8_t* header, uint32_t nonce0, int64_t n,
+                                 const uint32_t* table, int64_t rows, uint8_t* out) {
+  if (rows < 1 || n < 0) return -1;
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    uint8_t msg[80];
+    memcpy(msg, header, 76);
+    const uint32_t nonce = nonce0 + (uint32_t)i;
+    for (int b = 0; b < 4; ++b) msg[76 + b] = (uint8_t)(nonce >> (8 * b));
+    uint32_t s[16], mix[32];
+    uint32_t h = 2166136261u;
+    for (int b = 0; b < 80; ++b) h = fnv32(h, msg[b]);
+    s[0] = h;
+    for (int k = 1; k < 16; ++k) s[k] = fnv32(s[k - 1], (uint32_t)k);
+    for (int j = 0; j < 32; ++j) mix[j] = s[j % 16];
+    for (uint32_t a = 0; a < 64; ++a) {
+      const uint64_t p = (uint64_t)fnv32(a ^ s[0], mix[a % 32]) % (uint64_t)rows;
+      const uint32_t* row = table + p * 32;
+      for (int j = 0; j < 32; ++j) mix[j] = fnv32(mix[j], row[j]);
+    }
+    for (int k = 0; k < 8; ++k) {
+      const uint32_t v = fnv32(fnv32(fnv32(mix[4 * k], mix[4 * k + 1]), mix[4 * k + 2]), mix[4 * k + 3]);
+      for (int b = 0; b < 4; ++b) out[32 * i + 4 * k + b] = (uint8_t)(v >> (8 * b));
+    }
+  }
   return 0;
 }

@@ -233,6 +233,41 @@ def test_upsample_identity_scale():
     assert np.array_equal(oracle.upsample(x, 1), x.astype(np.float64))
 
 
+@pytest.mark.parametrize("shape,s", [((2, 3, 7, 9), 2), ((1, 2, 5, 4), 3), ((1, 1, 1, 6), 2), ((2, 2, 6, 1), 4)])
+def test_upsample_absmag_is_the_interpolation_of_abs(shape, s):
+    # The tolerance scale of every upsample check: sum_k |w_k x_k| over the
+    # four taps.  Bilinear weights are non-negative, so it equals the
+    # interpolation of |x|: against torch's bilinear interpolation of |x| in
+    # double (a library routine), and against the oracle's own upsample of |x|.
+    x = inputs.normal_image(shape, seed=31 + s)
+    mag = oracle.upsample_absmag(x, s)
+    ref = F.interpolate(torch.from_numpy(np.abs(x)).double(), scale_factor=s, mode="bilinear",
+                        align_corners=False).numpy()
+    np.testing.assert_allclose(mag, ref, rtol=1e-12, atol=0)
+    np.testing.assert_allclose(mag, oracle.upsample(np.abs(x), s), rtol=1e-12, atol=0)
+    # and it bounds the magnitude of the interpolated value itself
+    assert np.all(np.abs(oracle.upsample(x, s)) <= mag * (1 + 1e-12))
+
+
+def test_upsample_absmag_constant_and_sign():
+    # a constant c gives |c| everywhere; flipping the sign of the input
+    # changes nothing; a single non-zero input spreads exactly its weights
+    for c in (-2.5, 0.0, 3.0):
+        assert np.all(oracle.upsample_absmag(np.full((1, 1, 4, 5), c, np.float32), 2) == abs(c))
+    x = inputs.normal_image((1, 2, 6, 7), seed=33)
+    assert np.array_equal(oracle.upsample_absmag(x, 2), oracle.upsample_absmag(-x, 2))
+    one = np.zeros((1, 1, 4, 4), np.float32)
+    one[0, 0, 1, 2] = -1.0
+    # output row 3: source 1.25 -> rows 1 (0.75) and 2 (0.25); output column 5:
+    # source 2.25 -> columns 2 (0.75) and 3 (0.25): weight of x[1, 2] = 0.75 * 0.75
+    assert oracle.upsample_absmag(one, 2)[0, 0, 3, 5] == 0.5625
+    # output row 2 (source 0.75 -> rows 0 (0.25), 1 (0.75)), column 4 (source
+    # 1.75 -> columns 1 (0.25), 2 (0.75)): weight 0.75 * 0.75 again; column 6
+    # (source 2.75 -> columns 2 (0.25), 3 (0.75)): 0.75 * 0.25
+    assert oracle.upsample_absmag(one, 2)[0, 0, 2, 4] == 0.5625
+    assert oracle.upsample_absmag(one, 2)[0, 0, 2, 6] == 0.1875
+
+
 # ------------------------------------------------------------------- maxpool
 POOL_CASES = [((2, 3, 9, 11), (3, 3), 2, 1), ((1, 2, 8, 8), (2, 2), 2, 0), ((2, 1, 7, 5), (3, 2), 1, 1),
               ((1, 4, 12, 10), (3, 3), 3, 0), ((3, 2, 5, 6), (1, 1), 1, 0), ((1, 1, 4, 13), (2, 3), 1, 1)]
@@ -316,3 +351,29 @@ def test_maxpool_nan_propagates_and_minus_inf():
 def test_maxpool_rejects_windows_with_no_input():
     with pytest.raises(ValueError):
         oracle.maxpool(np.zeros((1, 1, 4, 4), np.float32), 2, 2, 1, 2)
+
+
+def test_openmp_build_gives_the_sequential_results():
+    # the OpenMP build spreads independent units over threads; every result
+    # must equal the sequential build's bit for bit
+    x = inputs.bn_input((3, 7, 9, 11), seed=40)
+    img = inputs.normal_image((2, 3, 9, 10), seed=41)
+    seeds = inputs.uint32_seeds(10_007, seed=42)
+    data = inputs.zipf_u8(100_003, seed=43)
+    table = inputs.eth_table(61, seed=44)
+    hdr = inputs.header80(45).tobytes()
+
+    def run():
+        return [*oracle.bn_stats(x), oracle.int_mix(seeds, 9), oracle.hist256(data),
+                oracle.im2col(img, 3, 3, 1, 1), oracle.upsample(img, 2), oracle.upsample_absmag(img, 3),
+                *oracle.maxpool(img, 3, 3, 2, 1), oracle.ethash_like(hdr, 5, table, 300)]
+
+    seq = run()
+    oracle.use_openmp(True)
+    try:
+        assert oracle.threads() >= 1
+        par = run()
+    finally:
+        oracle.use_openmp(False)
+    for a, b in zip(seq, par):
+        assert np.array_equal(a, b)

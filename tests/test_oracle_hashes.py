@@ -88,27 +88,41 @@ def _table(R, seed):
 
 
 def test_ethash_like_zero_table_closed_form():
-    # with an all-zero table every access multiplies each mix word by the FNV
-    # prime, whatever rows are read: mix_j = s_j * P^64, then the 4-to-1 fold
+    # With an all-zero table every access multiplies each mix word by the FNV
+    # prime, whatever rows are read: mix_j = s_(j mod 16) * P^64, then the
+    # 4-to-1 fold.  The seeds come from fnv1_32, the byte-wise FNV-1 that the
+    # published test values pin: s_k is FNV-1 of the instance's 80-byte
+    # message followed by the bytes 1..k.
     hdr = bytes(inputs.rng(8).integers(0, 256, size=80, dtype=np.uint8))
-    nonce = 99
-    words = [int.from_bytes(hdr[4 * k:4 * k + 4], "little") for k in range(19)] + [nonce]
-    h = 2166136261
-    for w in words:
-        h = ((h * 16777619) % 2 ** 32) ^ w
-    s = [h]
-    for k in range(1, 16):
-        s.append(((s[-1] * 16777619) % 2 ** 32) ^ k)
+    for nonce in (99, 0xFFFFFFFF, 0x01020304):
+        msg = hdr[:76] + nonce.to_bytes(4, "little")
+        s = [O.fnv1_32(msg + bytes(range(1, k + 1))) for k in range(16)]
+        p64 = pow(16777619, 64, 2 ** 32)
+        mix = [(s[j % 16] * p64) % 2 ** 32 for j in range(32)]
+        out = []
+        for k in range(8):
+            a = mix[4 * k]
+            for t in range(1, 4):
+                a = ((a * 16777619) % 2 ** 32) ^ mix[4 * k + t]
+            out.append(a)
+        want = b"".join(v.to_bytes(4, "little") for v in out)
+        assert O.ethash_like_one(hdr, nonce, np.zeros((37, 32), np.uint32)) == want
+
+
+def test_ethash_like_seed_takes_every_nonce_byte_little_endian():
+    # Nonces on both sides of each byte carry: under the zero-table closed form
+    # the first digest word is the fold of s_0..s_3 * P^64, and s_k is FNV-1 of
+    # the message with the nonce's four bytes in little-endian order.
+    hdr = bytes(range(80))
     p64 = pow(16777619, 64, 2 ** 32)
-    mix = [(s[j % 16] * p64) % 2 ** 32 for j in range(32)]
-    out = []
-    for k in range(8):
-        a = mix[4 * k]
+    for nonce in (0xFF, 0x100, 0xFFFF, 0x10000, 0xFFFFFF, 0x1000000):
+        msg = hdr[:76] + bytes([nonce & 0xFF, (nonce >> 8) & 0xFF, (nonce >> 16) & 0xFF, nonce >> 24])
+        mix = [(O.fnv1_32(msg + bytes(range(1, k + 1))) * p64) % 2 ** 32 for k in range(4)]
+        a = mix[0]
         for t in range(1, 4):
-            a = ((a * 16777619) % 2 ** 32) ^ mix[4 * k + t]
-        out.append(a)
-    want = b"".join(v.to_bytes(4, "little") for v in out)
-    assert O.ethash_like_one(hdr, nonce, np.zeros((37, 32), np.uint32)) == want
+            a = ((a * 16777619) % 2 ** 32) ^ mix[t]
+        got = O.ethash_like_one(hdr, nonce, np.zeros((1, 32), np.uint32))
+        assert int.from_bytes(got[:4], "little") == a, hex(nonce)
 
 
 def test_ethash_like_depends_exactly_on_the_rows_it_reads():
@@ -134,3 +148,15 @@ def test_ethash_like_rows_spread_over_the_table():
         O.ethash_like_one(hdr, n, T, rows)
     counts = np.bincount(rows, minlength=1024)
     assert counts.min() > 0 and counts.max() < 40
+
+
+def test_ethash_like_c_transcription_matches_the_python_definition():
+    # the C walk (used for the full-size checks) against the plain-integer one,
+    # with a nonce range that wraps past 2^32 and tables of 1, 37 and 4099 rows
+    import oracle
+    hdr = bytes(inputs.rng(12).integers(0, 256, size=80, dtype=np.uint8))
+    for rows, n0, n in ((4099, 12345, 40), (37, 0xFFFFFFF0, 33), (1, 7, 5)):
+        T = _table(rows, 13 + rows)
+        got = oracle.ethash_like(hdr, n0, T, n)
+        for i in range(n):
+            assert got[i].tobytes() == O.ethash_like_one(hdr, (n0 + i) & 0xFFFFFFFF, T), (rows, i)
