@@ -107,8 +107,11 @@ typedef enum {
  *                SHA256D, BLAKE2B, ETHASH: p[0] = first nonce (as uint32)
  *   in1          ETHASH: the table, uint32 [h][32] (h rows of 128 bytes,
  *                16-byte aligned, 1 <= h < 2^32); unused (NULL) otherwise.
- *                The row of access j of a hash is fnv(j ^ s0, mix[j % 32]) % h
- *                with fnv(a, b) = (a * 16777619) ^ b mod 2^32.
+ *                The seed s0 of a hash is FNV-1 (32 bits) of its 80-byte
+ *                message, s_k = fnv(s_(k-1), k) for k = 1..15 and the mix
+ *                starts as s_(j mod 16); the row of access j is
+ *                fnv(j ^ s0, mix[j % 32]) % h, with
+ *                fnv(a, b) = (a * 16777619) ^ b mod 2^32 (Ethash's access rule).
  * Input and output buffers must be 4-byte aligned (LDS_HIST input: any) and must
  * not overlap.  Element counts must stay below 2^31 per buffer. */
 typedef struct {

@@ -239,10 +239,15 @@ struct EthashLike {
   __device__ static void run(const DevTask& dt, const Part& p, Bar&, uint32_t*) {
     const EthArgs& a = dt.eth;
     if (a.n == 0) return;
-    uint32_t h19 = kOffset;  // the FNV chain over the 19 header words: uniform
+    // FNV-1 over the 76 header bytes that every instance shares: uniform
+    uint32_t h76 = kOffset;
 #pragma unroll
-    for (int k = 0; k < 19; ++k) h19 = fnv(h19, a.hdr[k]);
-    h19 = uniform(h19);
+    for (int k = 0; k < 19; ++k) {
+      const uint32_t w = a.hdr[k];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) h76 = fnv(h76, (w >> (8 * b)) & 0xFFu);
+    }
+    h76 = uniform(h76);
     const uint32_t lane = lane_id();
     const uint32_t grp = lane >> 3, gl = lane & 7u, q = gl & 3u;
     const uint32_t gbase = lane & ~7u;
@@ -252,7 +257,8 @@ struct EthashLike {
 #pragma unroll
       for (uint32_t h = 0; h < kChains; ++h) {
         const uint32_t ic = min(base + 8u * h + grp, a.n - 1u);
-        s0[h] = fnv(h19, a.nonce0 + ic);
+        const uint32_t nonce = a.nonce0 + ic;  // its four bytes, little-endian
+        s0[h] = fnv(fnv(fnv(fnv(h76, nonce & 0xFFu), (nonce >> 8) & 0xFFu), (nonce >> 16) & 0xFFu), nonce >> 24);
         uint32_t s[16];
         s[0] = s0[h];
 #pragma unroll

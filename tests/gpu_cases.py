@@ -12,7 +12,9 @@ Tolerances (written here, used by every GPU test):
 """
 from __future__ import annotations
 
+import contextlib
 import functools
+import hashlib
 
 import numpy as np
 import torch
@@ -24,6 +26,18 @@ from paper_2007_01277_amd import inputs
 
 DEV = "cuda"
 TOL = 1e-5
+
+
+@contextlib.contextmanager
+def parallel_oracle():
+    """Runs the oracle's OpenMP build inside the block (the same results as the
+    sequential build, which a CPU test checks): full-size checks over every
+    element then take seconds instead of minutes."""
+    oracle.use_openmp(True)
+    try:
+        yield
+    finally:
+        oracle.use_openmp(False)
 
 
 def dev(a: np.ndarray, offset: int = 0) -> torch.Tensor:
@@ -134,13 +148,17 @@ def up_case(shape, scale=2, seed=0, check_slice=None) -> Case:
     t = H.task_upsample(xd, out, scale)
 
     def check(outs):
-        sl = (slice(None), slice(None)) if check_slice is None else check_slice
-        xs = np.ascontiguousarray(xh[sl])
-        ref = oracle.upsample(xs, scale)
-        mag = oracle.upsample_absmag(xs, scale)
-        got = outs[0][sl].cpu().numpy().astype(np.float64)
-        err = np.abs(got - ref)
-        assert np.all(err <= TOL * mag), float(np.max(err / np.maximum(mag, 1e-300)))
+        if check_slice is not None:
+            slices = [check_slice]
+        else:  # image by image, so the double-precision references stay small
+            slices = [(slice(i, i + 1), slice(None)) for i in range(N)]
+        for sl in slices:
+            xs = np.ascontiguousarray(xh[sl])
+            ref = oracle.upsample(xs, scale)
+            mag = oracle.upsample_absmag(xs, scale)
+            got = outs[0][sl].cpu().numpy().astype(np.float64)
+            err = np.abs(got - ref)
+            assert np.all(err <= TOL * mag), (sl, float(np.max(err / np.maximum(mag, 1e-300))))
 
     return Case(t, {"in": xd, "outs": [out]}, check, f"upsample{tuple(shape)}x{scale}")
 
@@ -198,7 +216,12 @@ def hash_case(kind, n, seed=0, nonce0=None, rows=4099, sample=None) -> Case:
         t = (H.task_sha256d if kind == H.HF_SHA256D else H.task_blake2b)(hd, out, n0, n)
         bufs = {"in": hd, "outs": [out]}
 
-    def check(outs):
+    def check(outs, full=False):
+        """Every instance against the plain-integer oracle, or (sample set) the
+        first and last 64 plus `sample` drawn ones; with full=True also every
+        instance against the C transcription of the Ethash-like walk, or against
+        hashlib's SHA-256 / BLAKE2b (the library routines the oracle is pinned
+        to)."""
         got = outs[0].cpu().numpy().view(np.uint8).reshape(n, 32)
         if sample is None:
             idx = range(n)
@@ -208,6 +231,21 @@ def hash_case(kind, n, seed=0, nonce0=None, rows=4099, sample=None) -> Case:
         for i in idx:
             ref = _hash_ref(kind, hdr.tobytes(), n0, int(i), tkey)
             assert got[i].tobytes() == ref, (H.KIND_NAMES[kind], int(i))
+        if not full:
+            return
+        if kind == H.HF_ETHASH:
+            ref = oracle.ethash_like(hdr.tobytes(), n0, _eth_table(*tkey), n)
+            bad = np.nonzero(np.any(got != ref, axis=1))[0]
+            assert bad.size == 0, ("ethash", bad[:8])
+            return
+        head = hdr.tobytes()[:76]
+        for i in range(n):
+            m = head + ((n0 + i) & 0xFFFFFFFF).to_bytes(4, "little")
+            if kind == H.HF_SHA256D:
+                d = hashlib.sha256(hashlib.sha256(m).digest()).digest()
+            else:
+                d = hashlib.blake2b(m, digest_size=32).digest()
+            assert got[i].tobytes() == d, (H.KIND_NAMES[kind], i)
 
     return Case(t, bufs, check, f"{H.KIND_NAMES[kind]}({n},nonce0={n0:#x})")
 
