@@ -53,6 +53,8 @@ def parse():
                     help="block_a,block_b[,grid_a,grid_b]: skip the solo block and grid sweep")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle timing")
     ap.add_argument("--no-pairs", action="store_true", help="skip the summary of the other pairs")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched N-way and the learned-tuner legs")
     ap.add_argument("--no-cold", action="store_true",
                     help="skip the scrubbed-cache repeats (profiled runs: every traced launch is then a warm one)")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -203,27 +205,27 @@ class Workload:
         self.pair = H.make_pair(self.ta, self.tb)
         torch.cuda.synchronize()
 
-    def cpu_baseline(self):
-        """The CPU oracle (plain C, double accumulation, one thread) on the same step;
-        for the hash pair the Python oracle on a bounded sample, scaled."""
+    def _oracle_step(self):
+        """One pass of the oracle over the step's work; returns the two parts'
+        times in seconds and a description (the hash pair: a bounded sample)."""
         import numpy as np
 
         import oracle
-        t0 = time.perf_counter()
         if self.name == "ethash+sha256d":
             from oracle import hashes as OH
-            tab = self.table.cpu().numpy().view(np.uint32)
+            if not hasattr(self, "_tab"):
+                self._tab = self.table.cpu().numpy().view(np.uint32)
+            ke, ks = 20000, 4000  # a bounded sample of each kernel's instances, scaled below
             t0 = time.perf_counter()
-            ke, ks = 2000, 4000  # a bounded sample of each kernel's instances, scaled below
-            for i in range(ke):
-                OH.ethash_like_one(self.hdr.tobytes(), self.nonce + i, tab)
+            oracle.ethash_like(self.hdr.tobytes(), self.nonce, self._tab, ke)
             t1 = time.perf_counter()
-            OH.sha256d(self.hdr.tobytes(), self.nonce, range(ks))
+            OH.sha256d(self.hdr.tobytes(), self.nonce, range(ks))  # plain Python integers, one thread
             t2 = time.perf_counter()
-            full = (t1 - t0) * self.n_eth / ke + (t2 - t1) * self.n_sha / ks
-            return {"value": round(full * 1e3, 1), "unit": "ms/step", "cores": 1, "kind": "oracle",
-                    "sample": f"{ke} Ethash-like and {ks} SHA-256d hashes ({(t2 - t0):.1f} s, single thread), "
-                              f"scaled to the step's {self.n_eth} + {self.n_sha} hashes", "host": host_cpu()}
+            scale = (self.n_eth / ke, self.n_sha / ks)
+            return ((t1 - t0) * scale[0], (t2 - t1) * scale[1], t2 - t0,
+                    f"{ke} Ethash-like hashes (the C walk) and {ks} SHA-256d hashes (the Python oracle, "
+                    f"one thread in both legs), scaled to the step's {self.n_eth} + {self.n_sha} hashes")
+        t0 = time.perf_counter()
         if self.name == "bn_stats+int_mix":
             oracle.bn_stats(self.x)
             t1 = time.perf_counter()
@@ -240,9 +242,32 @@ class Workload:
             oracle.hist256(self.hist)
             parts = self.desc
         t2 = time.perf_counter()
-        return {"value": round((t2 - t0) * 1e3, 2), "unit": "ms/step", "cores": 1, "kind": "oracle",
-                "sample": f"the full step ({parts}): {(t1 - t0) * 1e3:.0f} ms + {(t2 - t1) * 1e3:.0f} ms, "
-                          "single thread", "host": host_cpu()}
+        return t1 - t0, t2 - t1, t2 - t0, f"the full step ({parts})"
+
+    def cpu_baseline(self):
+        """The CPU oracle (plain C, double accumulation) on the same step: its
+        OpenMP build on every host thread (`value`, `cores` = the threads it
+        used) and its sequential build on one thread (`single_thread`).  Both
+        builds compute the same results; only the loops over independent units
+        (channels, elements, planes, thread-private histograms, hashes) are
+        spread over threads."""
+        import oracle
+        legs = {}
+        for omp in (True, False):
+            oracle.use_openmp(omp)
+            try:
+                a, b, wall, what = self._oracle_step()
+                legs[omp] = (a, b, wall, what, oracle.threads())
+            finally:
+                oracle.use_openmp(False)
+        a, b, wall, what, th = legs[True]
+        a1, b1, wall1, _, _ = legs[False]
+        return {"value": round((a + b) * 1e3, 2), "unit": "ms/step", "cores": th, "kind": "oracle",
+                "sample": f"{what}: {a * 1e3:.0f} ms + {b * 1e3:.0f} ms on {th} threads "
+                          f"({wall:.1f} s of CPU work timed)",
+                "single_thread": {"value": round((a1 + b1) * 1e3, 2), "unit": "ms/step", "cores": 1,
+                                  "parts_ms": [round(a1 * 1e3, 1), round(b1 * 1e3, 1)]},
+                "host": host_cpu()}
 
 
 def measure(w, cfg_arg, blocks_arg, steps, warmup, log=sys.stderr, cold=True):
@@ -399,6 +424,75 @@ def measure(w, cfg_arg, blocks_arg, steps, warmup, log=sys.stderr, cold=True):
             "cold": cold, "regcap": regcap}
 
 
+def int_peak_leg(rounds=16384, reps=5):
+    """The measured integer-issue ceiling: the int_mix round from registers only
+    (four chains per lane, eight wavefronts per SIMD), best of `reps` launches."""
+    from paper_2007_01277_amd import hfuse as H
+    best = None
+    for _ in range(reps + 1):
+        ms, ops = H.hf_int_peak(rounds)
+        best = ms if best is None else min(best, ms)
+    return {"tlane_ops": round(ops / (best * 1e-3) / 1e12, 3), "ms": round(best, 5), "lane_ops": ops,
+            "of_nominal": round(ops / (best * 1e-3) / 1e12 / INT_PEAK_TOPS, 4)}
+
+
+def batch_leg(reps, log=sys.stderr):
+    """The batched N-way workload: 1000 small instances (2^12..2^18 elements,
+    six data kinds, fp32 and uint32) in groups of 2 to 4, the persistent fused
+    kernel (schedule from the batch tuner) replayed from a HIP graph against
+    the same instances launched back to back, round-robin on four streams and
+    as a HIP graph of the solo launches; every mode's outputs compared with
+    the back-to-back outputs bit for bit."""
+    import torch
+
+    from paper_2007_01277_amd import batch_bench as BB
+    kinds, logs, groups = BB.draw(1000)
+    w = BB.Workload(kinds, logs)
+    res, _ = BB.run_modes(w, groups, reps=reps, log=log)
+    alg = w.bytes()
+    out = {"instances": len(kinds), "groups": len(set(groups)), "elements": w.elements(), "alg_bytes": alg,
+           "batch_graph_ms": round(res["batch_graph_ms"], 5), "batch_ms": round(res["batch_ms"], 5),
+           "back_to_back_ms": round(res["back_to_back_ms"], 5), "streams4_ms": round(res["streams4_ms"], 5),
+           "graph_solo_ms": round(res["graph_solo_ms"], 5),
+           "speedup_vs_back_to_back": res["speedup_vs_back_to_back"],
+           "speedup_vs_streams4": res["speedup_vs_streams4"], "speedup_vs_graph_solo": res["speedup_vs_graph_solo"],
+           "hbm_gbps": res["batch_graph_GBps"], "hbm_frac": round(res["batch_graph_GBps"] / HBM_PEAK_GBS, 4),
+           "schedule": res["schedule"], "tune_s": res.get("tune_s"),
+           "bit_exact": all(res[k] for k in ("streams4_equal", "graph_solo_equal", "batch_equal",
+                                             "batch_graph_equal"))}
+    del w
+    torch.cuda.empty_cache()
+    return out
+
+
+def learned_tuner_leg(log=sys.stderr):
+    """The learned tuner at its workload's shape: 40 random pairs of the five
+    data kernels (2^16..2^26 elements, seed 2), every candidate of the
+    exhaustive search profiled (85 per pair), the cost model trained on the
+    GPU by the library's kernels on 50 configurations of each training pair and
+    evaluated on held-out pairs (4-fold cross-validation by pair).  Regret =
+    T(best of the model's top 3, profiled) / T(exhaustive best) - 1.  The
+    profiling cost counts the featurisation's solo launches next to the 3
+    profiled candidates."""
+    import torch
+
+    from paper_2007_01277_amd import learned_tuner as LT
+    t0 = time.time()
+    pairs = LT.draw_pairs(40, seed=2, kmin=16, kmax=26, kinds=LT.DATA_KINDS)
+    data = LT.collect(pairs, reps=10, seed=2, log=open(os.devnull, "w"))
+    t1 = time.time()
+    res = LT.evaluate(data, folds=4, per_pair=50, topk=3, epochs=500)
+    torch.cuda.empty_cache()
+    keep = ("regret_mlp_mean", "regret_mlp_max", "regret_naive_mean", "regret_r0_mean", "regret_random_mean",
+            "within_5pct_mlp", "rank_corr_mean", "n_samples", "n_candidates", "profiled_fraction",
+            "regret_mlp_mean_at_k", "cost_fraction_mean", "feature_launches")
+    out = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in res.items() if k in keep}
+    out.update({"pairs": 40, "per_pair_train": 50, "topk": 3, "folds": 4, "collect_s": round(t1 - t0, 1),
+                "train_eval_s": round(time.time() - t1, 1)})
+    print(f"learned tuner: top-3 regret {out['regret_mlp_mean']:.4f}", file=log, flush=True)
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -476,7 +570,12 @@ def main():
         res["tune"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in m["tune"].items()}
     if not a.no_cpu:
         res["cpu_baseline"] = w.cpu_baseline()
-    if not a.no_pairs and w.name == WORKLOADS[0]:
+    if w.bound == "alu":
+        res["int_peak"] = int_peak_leg()
+        res["roofline"]["measured_ceiling"] = res["int_peak"]["tlane_ops"]
+        res["roofline"]["frac_of_measured"] = round(res["roofline"]["achieved"] / res["int_peak"]["tlane_ops"], 4)
+    headline = w.name == WORKLOADS[0]
+    if not a.no_pairs and headline:
         del w
         torch.cuda.empty_cache()
         res["other_pairs"] = {}
@@ -497,6 +596,11 @@ def main():
                 "cold_cache": mo["cold"], "register_bound": mo["regcap"], "grid_tuned": mo["grid_tuned"]}
             del o
             torch.cuda.empty_cache()
+    if not a.no_extras and headline:
+        print("batch leg", file=sys.stderr, flush=True)
+        res["batch"] = batch_leg(max(5, min(a.steps, 20)))
+        print("learned tuner leg", file=sys.stderr, flush=True)
+        res["learned_tuner"] = learned_tuner_leg()
     print(json.dumps(res), flush=True)
     return 0
 

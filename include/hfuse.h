@@ -243,6 +243,9 @@ typedef struct {
   float t_naive_ms;       /* median time of the even split, block 1024, no cap       */
   float wall_s;           /* host wall time of the search                            */
   int32_t reps;           /* timed repetitions per candidate                         */
+  int32_t n_solo_launches;/* MLP: solo launches the featurisation made (each kernel at
+                             the three block sizes, 6 launches each)                 */
+  float solo_ms;          /* MLP: their summed time in milliseconds                  */
 } hf_tune_stats;
 /* Searches a fused configuration for the pair (Main search, Sec. III-B).  Each
  * profiled candidate is launched `HF_TUNE_REPS` (default 20) times after a warm-up
@@ -370,6 +373,13 @@ int hf_scrub(void* stream);
  * HF_TIMEOUT_MS). */
 int hf_selftest_barrier(int block, int split_waves, int iters_a, int iters_b, uint32_t seed, int grid,
                         void* stream, uint32_t* mismatches);
+/* Measured integer-issue ceiling of the int_mix round: `grid` workgroups of 256
+ * lanes (0: eight per CU, the resident maximum) each run `rounds` rounds of
+ * the round on four independent chains per lane from registers only (the
+ * int_mix body's instruction mix without its loads and stores).  Writes the
+ * lane-ops executed (8 per lane-round: 3 shifts, 3 xors, 1 multiply, 1 add)
+ * to lane_ops_out (may be NULL). */
+int hf_int_peak(int rounds, int grid, void* stream, float* ms_out, double* lane_ops_out);
 /* Keeps the GPU busy for about `ms` milliseconds (warm-up before measurements,
  * Sec. IV-A "Execution Time Measurement"). */
 int hf_warmup(int ms, void* stream);

@@ -48,14 +48,28 @@ def _compile(src, obj, defs, remarks):
     return obj, r.stderr
 
 
-def build(jobs: int | None = None, remarks: bool = False, verbose: bool = True) -> str:
-    """Compiles every HIP translation unit and links libhfuse.so; returns its path."""
+def _stale(src, obj):
+    """True unless `obj` is newer than its source and every header it may include."""
+    path = os.path.join(BUILD, obj)
+    if not os.path.exists(path):
+        return True
+    deps = [src, os.path.join(PKG, os.pardir, "include", "hfuse.h")] + \
+        [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hpp")]
+    return os.path.getmtime(path) < max(os.path.getmtime(d) for d in deps)
+
+
+def build(jobs: int | None = None, remarks: bool = False, verbose: bool = True,
+          incremental: bool = False) -> str:
+    """Compiles every HIP translation unit (with incremental=True only those
+    older than their sources or any header) and links libhfuse.so; returns
+    its path."""
     os.makedirs(BUILD, exist_ok=True)
     jobs = jobs or min(16, os.cpu_count() or 4)
     units = _units()
+    todo = [u for u in units if not incremental or remarks or _stale(u[0], u[1])]
     logs = {}
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        futs = [ex.submit(_compile, s, o, d, remarks) for s, o, d in units]
+        futs = [ex.submit(_compile, s, o, d, remarks) for s, o, d in todo]
         for f in cf.as_completed(futs):
             obj, err = f.result()
             logs[obj] = err
@@ -75,4 +89,4 @@ def build(jobs: int | None = None, remarks: bool = False, verbose: bool = True) 
 
 if __name__ == "__main__":
     import sys
-    build(remarks="--remarks" in sys.argv)
+    build(remarks="--remarks" in sys.argv, incremental="--incremental" in sys.argv)

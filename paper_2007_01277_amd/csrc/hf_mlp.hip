@@ -326,7 +326,10 @@ static void alg_work(const hf_task* t, double* bytes, double* ops) {
   }
 }
 
-static int solo_feat(DeviceState* s, const hf_task* t, hipStream_t st, SoloFeat* f) {
+// Times the task alone at each block size (6 launches each, the first a warm
+// up; the median of the other five).  `cost`, if given, accumulates the
+// launches made and their summed time in milliseconds.
+static int solo_feat(DeviceState* s, const hf_task* t, hipStream_t st, SoloFeat* f, FeatCost* cost) {
   f->kind = t->kind;
   alg_work(t, &f->bytes, &f->ops);
   double best = 1e30;
@@ -342,6 +345,10 @@ static int solo_feat(DeviceState* s, const hf_task* t, hipStream_t st, SoloFeat*
       if ((rc = wait_event(s->ev_stop)) != HF_OK) return rc;
       float ms = 0.f;
       if ((e = hipEventElapsedTime(&ms, s->ev_start, s->ev_stop)) != hipSuccess) return record_hip(e);
+      if (cost) {
+        cost->launches += 1;
+        cost->ms += ms;
+      }
       if (r > 0) ts.push_back(ms);  // the first launch warms up
     }
     std::sort(ts.begin(), ts.end());
@@ -411,11 +418,12 @@ static void fill_features(const SoloFeat& fa0, const SoloFeat& fb0, const hf_con
   g[9] = l2(fa.t_ms + fb.t_ms);
 }
 
-int featurize(DeviceState* s, const hf_pair* pr, const hf_config* cfg, int n, hipStream_t st, float* X) {
+int featurize(DeviceState* s, const hf_pair* pr, const hf_config* cfg, int n, hipStream_t st, float* X,
+              FeatCost* cost) {
   SoloFeat fa, fb;
   int rc;
-  if ((rc = solo_feat(s, &pr->a, st, &fa)) != HF_OK) return rc;
-  if ((rc = solo_feat(s, &pr->b, st, &fb)) != HF_OK) return rc;
+  if ((rc = solo_feat(s, &pr->a, st, &fa, cost)) != HF_OK) return rc;
+  if ((rc = solo_feat(s, &pr->b, st, &fb, cost)) != HF_OK) return rc;
   for (int i = 0; i < n; ++i) {
     hf_kernel_info info;
     if ((rc = hf_fused_info(pr->a.kind, pr->b.kind, cfg[i].block, cfg[i].vgpr_cap, &info)) != HF_OK) return rc;
@@ -444,15 +452,16 @@ static int predict(MlpModel* M, const float* X, int n, float* y, hipStream_t st)
   return HF_OK;
 }
 
-int mlp_rank(DeviceState* s, const hf_pair* pr, const std::vector<hf_config>& cands, std::vector<int>* order) {
+int mlp_rank(DeviceState* s, const hf_pair* pr, const std::vector<hf_config>& cands, hipStream_t st,
+             std::vector<int>* order, FeatCost* cost) {
   MlpModel* M = nullptr;
   int rc = model(&M);
   if (rc != HF_OK) return rc;
   if (!M->trained || M->d != kFeat) return HF_ENOMODEL;
   const int n = (int)cands.size();
   std::vector<float> X((size_t)n * kFeat), y(n);
-  if ((rc = featurize(s, pr, cands.data(), n, nullptr, X.data())) != HF_OK) return rc;
-  if ((rc = predict(M, X.data(), n, y.data(), nullptr)) != HF_OK) return rc;
+  if ((rc = featurize(s, pr, cands.data(), n, st, X.data(), cost)) != HF_OK) return rc;
+  if ((rc = predict(M, X.data(), n, y.data(), st)) != HF_OK) return rc;
   order->resize(n);
   std::iota(order->begin(), order->end(), 0);
   std::stable_sort(order->begin(), order->end(), [&](int a, int b) { return y[a] < y[b]; });
@@ -669,7 +678,7 @@ int hf_featurize(const hf_pair* pr, const hf_config* cfg, int n, void* stream, f
     if ((rc = hf_validate_fused(pr, &cfg[i])) != HF_OK) return rc;
   DeviceState* s = device_state(&rc);
   if (!s) return rc;
-  return featurize(s, pr, cfg, n, static_cast<hipStream_t>(stream), X_out);
+  return featurize(s, pr, cfg, n, static_cast<hipStream_t>(stream), X_out, nullptr);
 }
 
 }  // extern "C"

@@ -664,6 +664,20 @@ __global__ void __launch_bounds__(BLOCK) k_barrier_selftest(uint32_t w1, uint32_
   if (bad) __hip_atomic_fetch_add(errors, bad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// The integer-issue ceiling: the int_mix round on four independent chains per
+// lane, as the int_mix body runs it, from registers only (no memory traffic
+// in the loop), so its rate is what the VALU sustains for this instruction mix.
+__global__ void __launch_bounds__(256) k_int_peak(uint32_t* sink, uint32_t rounds) {
+  uint32_t a = threadIdx.x, b = blockIdx.x, c = threadIdx.x ^ 0x5555u, d = blockIdx.x * 977u + threadIdx.x;
+  for (uint32_t r = 0; r < rounds; ++r) {
+    a = IntMix::round1(a, r);
+    b = IntMix::round1(b, r);
+    c = IntMix::round1(c, r);
+    d = IntMix::round1(d, r);
+  }
+  if ((a ^ b ^ c ^ d) == 0x12345678u) sink[blockIdx.x % kSinkWords] = a;  // keeps the loop alive
+}
+
 __global__ void __launch_bounds__(256) k_spin(uint32_t* sink, uint32_t iters) {
   uint32_t x = threadIdx.x ^ (blockIdx.x << 10);
   for (uint32_t i = 0; i < iters; ++i) x = IntMix::round1(x, i);
@@ -926,6 +940,28 @@ int hf_selftest_barrier(int block, int split_waves, int iters_a, int iters_b, ui
   if ((e = hipMemcpyAsync(mismatches, errors, 4, hipMemcpyDeviceToHost, st)) != hipSuccess) return record_hip(e);
   if ((e = hipEventRecord(s->ev_stop, st)) != hipSuccess) return record_hip(e);
   return wait_event(s->ev_stop);
+}
+
+int hf_int_peak(int rounds, int grid, void* stream, float* ms_out, double* lane_ops_out) {
+  if (rounds < 1 || grid < 0 || grid > (1 << 20)) return HF_EINVAL;
+  int rc;
+  DeviceState* s = device_state(&rc);
+  if (!s) return rc;
+  if (!s->warm) {
+    hipError_t e = hipMalloc(&s->warm, 1 << 16);
+    if (e != hipSuccess) {
+      record_hip(e);
+      return HF_ENOMEM;
+    }
+  }
+  if (grid == 0) grid = s->num_cus * 8;  // 2048 lanes per CU: eight wavefronts per SIMD
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if ((rc = timed_begin(s, st, ms_out)) != HF_OK) return rc;
+  hipLaunchKernelGGL(k_int_peak, dim3(grid), dim3(256), 0, st, static_cast<uint32_t*>(s->warm), (uint32_t)rounds);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return record_hip(e);
+  if (lane_ops_out) *lane_ops_out = 8.0 * 4.0 * 256.0 * (double)grid * (double)rounds;
+  return timed_end(s, st, ms_out);
 }
 
 int hf_warmup(int ms, void* stream) {

@@ -25,6 +25,13 @@ struct DeviceState {
   void* warm = nullptr;                              // sink of the warm-up kernel
 };
 
+// Solo launches a featurisation made and their summed time (the learned
+// tuner's profiling cost besides the candidates it profiles).
+struct FeatCost {
+  int launches = 0;
+  double ms = 0.0;
+};
+
 int record_hip(hipError_t e);
 DeviceState* device_state(int* status);
 const KernelEntry* find_kernel(int ka, int kb, int block, int cap);

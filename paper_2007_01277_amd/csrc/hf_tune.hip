@@ -114,8 +114,8 @@ int solo_vgprs(DeviceState* s, int kind, int* v) {
 }
 
 // Ranks candidates with the learned model; defined in hf_mlp.hip.
-int mlp_rank(DeviceState* s, const hf_pair* pr, const std::vector<hf_config>& cands,
-             std::vector<int>* order);
+int mlp_rank(DeviceState* s, const hf_pair* pr, const std::vector<hf_config>& cands, hipStream_t st,
+             std::vector<int>* order, FeatCost* cost);
 
 }  // namespace hf
 
@@ -172,8 +172,9 @@ int hf_tune(const hf_pair* pr, int method, int block, int topk, void* stream, hf
 
   std::vector<int> order(cands.size());
   for (size_t i = 0; i < cands.size(); ++i) order[i] = (int)i;
+  FeatCost fcost;
   if (method == HF_TUNE_MLP) {
-    if ((rc = mlp_rank(s, pr, cands, &order)) != HF_OK) return rc;
+    if ((rc = mlp_rank(s, pr, cands, st, &order, &fcost)) != HF_OK) return rc;
     if ((int)order.size() > topk) order.resize(topk);
   }
 
@@ -226,6 +227,8 @@ int hf_tune(const hf_pair* pr, int method, int block, int topk, void* stream, hf
     float tn = 0.f;
     if ((rc = profile(s, pr, naive, reps, st, &tn)) != HF_OK) return rc;
     stats->t_naive_ms = tn;
+    stats->n_solo_launches = fcost.launches;
+    stats->solo_ms = (float)fcost.ms;
     stats->wall_s = std::chrono::duration<float>(std::chrono::steady_clock::now() - t0).count();
   }
   return HF_OK;

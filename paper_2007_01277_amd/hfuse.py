@@ -62,7 +62,8 @@ class hf_kernel_info(ctypes.Structure):
 class hf_tune_stats(ctypes.Structure):
     _fields_ = [("n_candidates", ctypes.c_int32), ("n_profiled", ctypes.c_int32),
                 ("t_best_ms", ctypes.c_float), ("t_naive_ms", ctypes.c_float),
-                ("wall_s", ctypes.c_float), ("reps", ctypes.c_int32)]
+                ("wall_s", ctypes.c_float), ("reps", ctypes.c_int32),
+                ("n_solo_launches", ctypes.c_int32), ("solo_ms", ctypes.c_float)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -117,6 +118,7 @@ SIGNATURES = {
     "hf_read": (_I, [_P, ctypes.c_int64, _P, _F]),
     "hf_scrub": (_I, [_P]),
     "hf_warmup": (_I, [_I, _P]),
+    "hf_int_peak": (_I, [_I, _I, _P, _F, ctypes.POINTER(ctypes.c_double)]),
     "hf_selftest_barrier": (_I, [_I, _I, _I, _I, ctypes.c_uint32, _I, _P, ctypes.POINTER(ctypes.c_uint32)]),
 }
 
@@ -536,3 +538,12 @@ def hf_selftest_barrier(block: int, split_waves: int, iters_a: int, iters_b: int
 
 def hf_warmup(ms: int = 500, stream=None):
     _check(lib().hf_warmup(ms, _stream(stream)), "hf_warmup")
+
+
+def hf_int_peak(rounds: int = 16384, grid: int = 0, stream=None):
+    """(ms, lane-ops) of one launch of the register-only int_mix round loop:
+    the measured integer-issue ceiling."""
+    ms = ctypes.c_float(0.0)
+    ops = ctypes.c_double(0.0)
+    _check(lib().hf_int_peak(rounds, grid, _stream(stream), ctypes.byref(ms), ctypes.byref(ops)), "hf_int_peak")
+    return ms.value, ops.value

@@ -203,6 +203,20 @@ def collect(pairs, reps: int = 10, seed: int = 2, log=sys.stderr, store: str = "
 
 
 SUM_SOLO = H.MLP_FEATURES - 1  # feature index of log2(sum of the best solo times)
+PER_KERNEL = len(H.KIND_NAMES) + 7  # features per kernel; the first kernel's come first
+FEATURE_LAUNCHES = 2 * 3 * 6  # featurisation: each kernel alone at three block sizes, six launches each
+TUNE_REPS = 20  # hf_tune's timed launches per candidate (after one untimed launch)
+
+
+def featurisation_ms(x) -> float:
+    """Time the featurisation's solo launches take, from one candidate's
+    features: six launches of each kernel at each block size, whose median
+    times are features (log2 ms) of the candidate."""
+    t = 0.0
+    for k in range(2):
+        o = PER_KERNEL * k + len(H.KIND_NAMES)
+        t += 6.0 * sum(2.0 ** float(x[o + b]) for b in range(3))
+    return t
 
 
 def evaluate(data, folds: int = 4, per_pair: int = 14, topk: int = 3, epochs: int = 500,
@@ -252,10 +266,14 @@ def evaluate(data, folds: int = 4, per_pair: int = 14, topk: int = 3, epochs: in
                    "regret_r0": float(2 ** (ty[keys.index(r0)] - best) - 1),
                    "regret_random": float(2 ** (ty[rnd].min() - best) - 1),
                    "rank_corr": float(np.corrcoef(np.argsort(np.argsort(pred)), np.argsort(np.argsort(ty)))[0, 1]),
+                   # profiling cost of the learned tuner (featurisation + its top k) over the exhaustive one
+                   "cost_fraction": float((featurisation_ms(X[idx[0]]) + (TUNE_REPS + 1) * np.sum(2.0 ** ty[top]))
+                                          / ((TUNE_REPS + 1) * np.sum(2.0 ** ty))),
                    "pred_rmse_log2": float(np.sqrt(np.mean((pred - yrel[idx]) ** 2)))}
             res["per_pair"].append(rec)
     pp = res["per_pair"]
-    for k in ("regret_mlp", "regret_naive", "regret_r0", "regret_random", "rank_corr", "pred_rmse_log2"):
+    for k in ("regret_mlp", "regret_naive", "regret_r0", "regret_random", "rank_corr", "pred_rmse_log2",
+              "cost_fraction"):
         v = np.array([r[k] for r in pp])
         res[k + "_mean"] = float(v.mean())
         res[k + "_max"] = float(v.max())
@@ -263,6 +281,7 @@ def evaluate(data, folds: int = 4, per_pair: int = 14, topk: int = 3, epochs: in
     res["regret_mlp_mean_at_k"] = {int(k): float(np.mean([r["regret_mlp_at_k"][k] for r in pp])) for k in ks}
     res["regret_random_mean_at_k"] = {int(k): float(np.mean([r["regret_random_at_k"][k] for r in pp])) for k in ks}
     res["profiled_fraction"] = topk / len(keys)
+    res["feature_launches"] = FEATURE_LAUNCHES
     res["train_loss"] = [float(v) for v in train_loss]
     res["n_samples"] = int(len(y))
     return res

@@ -286,3 +286,4 @@ def test_tuner_sample_store_skips_a_cut_line(tmp_path):
     LT._append(str(p), {"key": "c", "X": [[2.0]], "y": [1.5]})  # after the cut line, on a line of its own
     d = LT._load_store(str(p))
     assert sorted(d) == ["a", "c"] and len(p.read_text().splitlines()) == 3
+

@@ -129,7 +129,35 @@ def test_hf_tune_mlp_profiles_only_topk():
     pr = H.make_pair(ia.task, ib.task)
     best, st = H.hf_tune(pr, H.HF_TUNE_MLP, 0, 3)
     assert st["n_profiled"] == 3 and st["n_candidates"] == 85
+    # the featurisation's own cost: two kernels x three blocks x six launches
+    assert st["n_solo_launches"] == 36 and st["solo_ms"] > 0
     assert H.hf_validate_fused(pr, best) == H.HF_OK
+
+
+def test_hf_tune_mlp_orders_its_launches_on_the_callers_stream():
+    """hf_tune(MLP) on a non-blocking stream right after an unsynchronised
+    fused launch on that stream: the featurisation's solo launches run on the
+    same stream, after it, so both tasks' outputs are right afterwards and
+    their (caller-provided) scratch is left zero-filled."""
+    from tests import gpu_cases as G
+    pairs = LT.draw_pairs(4, seed=16, kmin=16, kmax=18, kinds=LT.DATA_KINDS)
+    data = LT.collect(pairs, reps=2, seed=16)
+    H.hf_mlp_init(D, 1)
+    H.hf_mlp_train(data["X"], data["y"] - data["X"][:, LT.SUM_SOLO], epochs=100, lr=1e-3)
+    ca, cb = G.bn_case((16, 64, 28, 28), seed=17), G.hist_case(1 << 22, seed=18)
+    scr = [torch.zeros(H.hf_scratch_bytes(c.task) // 4, dtype=torch.int32, device="cuda") for c in (ca, cb)]
+    ca.task.scratch, cb.task.scratch = scr[0].data_ptr(), scr[1].data_ptr()
+    pr = H.make_pair(ca.task, cb.task)
+    side = torch.cuda.Stream()  # created non-blocking by torch
+    torch.cuda.synchronize()
+    for c in (ca, cb):
+        c.reset()
+    H.hf_run_fused_cfg(pr, H.hf_config(2, 256, 0, 0), stream=side)
+    H.hf_tune(pr, H.HF_TUNE_MLP, 0, 2, stream=side)
+    torch.cuda.synchronize()
+    ca.check(ca.outputs())
+    cb.check(cb.outputs())
+    assert all(int(t.abs().sum()) == 0 for t in scr)
 
 
 def test_sample_store_resumes_an_interrupted_sweep(tmp_path, monkeypatch):
