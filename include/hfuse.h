@@ -50,7 +50,9 @@ typedef enum {
   HF_EHIP = -3,          /* a HIP runtime call failed; see hf_last_hip_error()          */
   HF_ETIMEOUT = -4,      /* the watchdog (HF_TIMEOUT_MS) expired while waiting          */
   HF_ENOMEM = -5,        /* device allocation failed                                    */
-  HF_ENOMODEL = -6       /* learned tuner asked for before a model was trained/loaded   */
+  HF_ENOMODEL = -6,      /* learned tuner asked for before a model was trained/loaded   */
+  HF_ESCRATCH = -7       /* hf_run_fused_noalloc: the tasks' scratch exceeds its static
+                            buffer (HF_NOALLOC_SCRATCH_BYTES)                          */
 } hf_status;
 
 /* ---------------------------------------------------------------- kernel kinds */
@@ -196,6 +198,23 @@ int hf_run_fused(const hf_pair* pr, int split_num, int split_den, int block,
 /* Same, with an explicit hf_config (also fixes the grid). */
 int hf_run_fused_cfg(const hf_pair* pr, const hf_config* cfg, void* stream,
                      float* ms_out);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * fused launch as hf_run_fused_cfg, whose tasks without caller scratch get
+ * their scratch from a static device array of HF_NOALLOC_SCRATCH_BYTES bytes
+ * (one per device, loaded with the library's code object, held until the
+ * process ends) instead of the library's allocated arena.  The call makes no
+ * allocation on any path (no hipMalloc / hipFree); it enqueues a small kernel
+ * that zeroes the scratch regions it uses, then the fused kernel, on `stream`,
+ * and returns without waiting (the caller times it with its own events).
+ * Returns HF_ESCRATCH, before any HIP call, when the two tasks' regions
+ * (hf_scratch_bytes each, rounded up to 256 bytes) exceed the array, e.g.
+ * bn_stats over more than about 2^28 elements.  Every call on one device
+ * shares that device's array: calls that overlap in time on one device race,
+ * so callers on several streams must order them. */
+#define HF_NOALLOC_SCRATCH_BYTES (4 << 20)
+int hf_run_fused_noalloc(const hf_pair* pr, const hf_config* cfg, void* stream);
 
 /* Vertical fusion, the comparator of Sec. II-B / IV-A: one launch in which
  * every thread of a `block`-lane workgroup runs task a's body and then task b's,

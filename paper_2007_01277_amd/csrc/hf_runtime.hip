@@ -69,6 +69,14 @@ bool cap_in_menu(int cap) {
   return cap == 0 || cap == 64 || cap == 80 || cap == 96 || cap == 128;
 }
 
+// ------------------------------------------------------------------ static scratch
+// Scratch of hf_run_fused_noalloc: a fixed array in the code object, one copy
+// per device, held until the process ends.  In host code `scratch` is only a
+// stand-in for the symbol, never an address: the device address is looked up
+// once per device (hipGetSymbolAddress, with that device current) when the
+// device's state is set up, and host code uses that address only.
+static __device__ __align__(256) uint8_t scratch[HF_NOALLOC_SCRATCH_BYTES];
+
 // ------------------------------------------------------------------ device state
 static std::mutex g_mu;
 static std::vector<DeviceState*> g_devs;
@@ -100,6 +108,10 @@ DeviceState* device_state(int* status) {
       }
     if ((e = hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming)) != hipSuccess ||
         (e = hipEventCreateWithFlags(&s->ev_join, hipEventDisableTiming)) != hipSuccess) {
+      *status = record_hip(e);
+      return nullptr;
+    }
+    if ((e = hipGetSymbolAddress(&s->static_scratch, HIP_SYMBOL(scratch))) != hipSuccess) {
       *status = record_hip(e);
       return nullptr;
     }
@@ -664,6 +676,13 @@ __global__ void __launch_bounds__(BLOCK) k_barrier_selftest(uint32_t w1, uint32_
   if (bad) __hip_atomic_fetch_add(errors, bad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Zeroes n words (the static scratch before an allocation-free launch; a
+// kernel rather than a memset, so that a captured graph holds no memset node).
+__global__ void __launch_bounds__(256) k_zero_words(uint32_t* __restrict__ p, uint32_t n) {
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0u;
+}
+
 // The integer-issue ceiling: the int_mix round on four independent chains per
 // lane, as the int_mix body runs it, from registers only (no memory traffic
 // in the loop), so its rate is what the VALU sustains for this instruction mix.
@@ -710,6 +729,7 @@ const char* hf_strerror(int status) {
     case HF_ETIMEOUT: return "timed out waiting for the GPU";
     case HF_ENOMEM: return "device allocation failed";
     case HF_ENOMODEL: return "no learned cost model trained or loaded";
+    case HF_ESCRATCH: return "the tasks need more scratch than the allocation-free entry point's static buffer holds";
   }
   return "unknown status";
 }
@@ -768,6 +788,41 @@ int hf_run_fused_cfg(const hf_pair* pr, const hf_config* cfg, void* stream, floa
   if ((rc = timed_begin(s, st, ms_out)) != HF_OK) return rc;
   if ((rc = launch_fused(s, pr, cfg, st, nullptr)) != HF_OK) return rc;
   return timed_end(s, st, ms_out);
+}
+
+int hf_run_fused_noalloc(const hf_pair* pr, const hf_config* cfg, void* stream) {
+  int rc = hf_validate_fused(pr, cfg);
+  if (rc != HF_OK) return rc;
+  // host only: where each task without caller scratch gets its region
+  hf_pair p = *pr;
+  hf_task* ts[2] = {&p.a, &p.b};
+  size_t off[2] = {0, 0}, total = 0;
+  bool mine[2] = {false, false};
+  for (int i = 0; i < 2; ++i) {
+    const int64_t need = scratch_bytes(ts[i]);
+    if (need > 0 && !ts[i]->scratch) {
+      mine[i] = true;
+      off[i] = total;
+      total += ((size_t)need + 255) & ~size_t(255);
+    }
+  }
+  if (total > (size_t)HF_NOALLOC_SCRATCH_BYTES) return HF_ESCRATCH;
+  DeviceState* s = device_state(&rc);
+  if (!s) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (total > 0) {
+    uint8_t* base = static_cast<uint8_t*>(s->static_scratch);
+    for (int i = 0; i < 2; ++i)
+      if (mine[i]) ts[i]->scratch = base + off[i];
+    // the regions must start zero-filled; the array keeps whatever the last
+    // call on this device left in it
+    const uint32_t words = (uint32_t)(total / 4);
+    const int grid = (int)std::min<uint32_t>((words + 255u) / 256u, 1024u);
+    hipLaunchKernelGGL(k_zero_words, dim3(grid), dim3(256), 0, st, reinterpret_cast<uint32_t*>(base), words);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return record_hip(e);
+  }
+  return launch_fused(s, &p, cfg, st, nullptr);
 }
 
 int hf_run_fused(const hf_pair* pr, int split_num, int split_den, int block, int vgpr_cap,

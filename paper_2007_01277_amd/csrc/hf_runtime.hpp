@@ -23,6 +23,7 @@ struct DeviceState {
   std::vector<Slot> slots;                           // scratch arena, one slot per concurrent task
   void* scrub = nullptr;                             // 1 GiB cache scrub buffer
   void* warm = nullptr;                              // sink of the warm-up kernel
+  void* static_scratch = nullptr;                    // device address of the static scratch array
 };
 
 // Solo launches a featurisation made and their summed time (the learned

@@ -13,7 +13,8 @@ import os
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("HFUSE_LIB") or os.path.join(PKG, "libhfuse.so")
 
-HF_OK, HF_EINVAL, HF_EUNSUPPORTED, HF_EHIP, HF_ETIMEOUT, HF_ENOMEM, HF_ENOMODEL = 0, -1, -2, -3, -4, -5, -6
+HF_OK, HF_EINVAL, HF_EUNSUPPORTED, HF_EHIP, HF_ETIMEOUT, HF_ENOMEM, HF_ENOMODEL, HF_ESCRATCH = 0, -1, -2, -3, -4, -5, -6, -7
+HF_NOALLOC_SCRATCH_BYTES = 4 << 20
 (HF_BN_STATS, HF_INT_MIX, HF_IM2COL, HF_LDS_HIST, HF_UPSAMPLE, HF_MAXPOOL, HF_SHA256D, HF_BLAKE2B,
  HF_ETHASH) = range(9)
 KIND_NAMES = ["bn_stats", "int_mix", "im2col", "lds_hist", "upsample", "maxpool", "sha256d", "blake2b", "ethash"]
@@ -88,6 +89,7 @@ SIGNATURES = {
     "hf_run_unfused": (_I, [ctypes.POINTER(hf_pair), _I, _I, _I, _P, _P, _F]),
     "hf_run_fused": (_I, [ctypes.POINTER(hf_pair), _I, _I, _I, _I, _P, _F]),
     "hf_run_fused_cfg": (_I, [ctypes.POINTER(hf_pair), ctypes.POINTER(hf_config), _P, _F]),
+    "hf_run_fused_noalloc": (_I, [ctypes.POINTER(hf_pair), ctypes.POINTER(hf_config), _P]),
     "hf_run_vfused": (_I, [ctypes.POINTER(hf_pair), _I, _I, _P, _F]),
     "hf_fused_info": (_I, [_I, _I, _I, _I, ctypes.POINTER(hf_kernel_info)]),
     "hf_solo_info": (_I, [_I, _I, ctypes.POINTER(hf_kernel_info)]),
@@ -312,6 +314,12 @@ def hf_run_fused_cfg(pr: hf_pair, cfg: hf_config, stream=None, timed=False):
     _check(lib().hf_run_fused_cfg(ctypes.byref(pr), ctypes.byref(cfg), _stream(stream),
                                   ctypes.byref(ms) if ms is not None else None), "hf_run_fused_cfg")
     return ms.value if ms is not None else None
+
+
+def hf_run_fused_noalloc(pr: hf_pair, cfg: hf_config, stream=None):
+    """The fused launch with the library's static scratch (no allocation)."""
+    _check(lib().hf_run_fused_noalloc(ctypes.byref(pr), ctypes.byref(cfg), _stream(stream)),
+           "hf_run_fused_noalloc")
 
 
 def hf_run_vfused(pr: hf_pair, block: int = 256, grid: int = 0, stream=None, timed=False):

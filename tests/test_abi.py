@@ -30,7 +30,7 @@ def test_library_exports_every_declared_function():
 
 def test_strerror_and_version():
     L = H.lib()
-    for code in (0, -1, -2, -3, -4, -5, -6, -99):
+    for code in (0, -1, -2, -3, -4, -5, -6, -7, -99):
         assert L.hf_strerror(code)
     assert b"gfx950" in L.hf_version()
 
@@ -287,3 +287,23 @@ def test_tuner_sample_store_skips_a_cut_line(tmp_path):
     d = LT._load_store(str(p))
     assert sorted(d) == ["a", "c"] and len(p.read_text().splitlines()) == 3
 
+
+def test_noalloc_rejects_before_touching_the_gpu():
+    # bad configurations, and tasks whose scratch exceeds the static array
+    # (bn_stats of 2^31 - 1 - 2^20 elements in one channel needs ~16 MiB)
+    L = H.lib()
+    pr = H.make_pair(_bn(), _mix())
+    assert L.hf_run_fused_noalloc(ctypes.byref(pr), ctypes.byref(H.hf_config(4, 256, 0, 0)), None) == H.HF_EINVAL
+    assert L.hf_run_fused_noalloc(None, ctypes.byref(H.hf_config(2, 256, 0, 0)), None) == H.HF_EINVAL
+    big = _bn(n=1, c=1, h=1, w=(1 << 31) - 1 - (1 << 20))
+    assert H.hf_scratch_bytes(big) > H.HF_NOALLOC_SCRATCH_BYTES
+    pr = H.make_pair(big, _hist())
+    assert L.hf_run_fused_noalloc(ctypes.byref(pr), ctypes.byref(H.hf_config(2, 256, 0, 0)), None) == H.HF_ESCRATCH
+    # two tasks that each fit but not together
+    half = H.HF_NOALLOC_SCRATCH_BYTES // 2
+    w = 1024 * (half // 8)  # (mean, M2) per 1024-element unit: just over half the array
+    a, b = _bn(n=1, c=1, h=1, w=w), _bn(n=1, c=1, h=1, w=w)
+    b.in_, b.out0, b.out1 = _fake_ptr(1 << 24), _fake_ptr(1 << 25), _fake_ptr(1 << 26)
+    assert H.hf_scratch_bytes(a) <= H.HF_NOALLOC_SCRATCH_BYTES
+    pr = H.make_pair(a, b)
+    assert L.hf_run_fused_noalloc(ctypes.byref(pr), ctypes.byref(H.hf_config(2, 256, 0, 0)), None) == H.HF_ESCRATCH
