@@ -87,6 +87,50 @@ def build(jobs: int | None = None, remarks: bool = False, verbose: bool = True,
     return LIB
 
 
+ASAN_DIR = os.path.join(BUILD, "asan")
+ASAN_EXE = os.path.join(ASAN_DIR, "host_checks")
+HOST_UNITS = ("hf_runtime", "hf_tune", "hf_mlp", "hf_batch")
+
+
+def build_asan(jobs: int | None = None) -> str:
+    """Builds tests/asan/host_checks.cpp against the library with the host side
+    of its host translation units compiled under AddressSanitizer (the device
+    code is unchanged; the kernel-table objects of the regular build are
+    reused).  Returns the executable's path; it runs without a GPU."""
+    needed = [os.path.join(BUILD, o) for _, o, _ in _units()]
+    if not os.path.exists(LIB) or not all(os.path.exists(o) for o in needed):
+        build(jobs=jobs)
+    os.makedirs(ASAN_DIR, exist_ok=True)
+    asan = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fno-omit-frame-pointer", "-g"]
+    jobs = jobs or min(16, os.cpu_count() or 4)
+    units = [(os.path.join(CSRC, u + ".hip"), os.path.join(ASAN_DIR, u + ".o")) for u in HOST_UNITS]
+
+    def comp(src, obj):
+        r = subprocess.run([HIPCC] + FLAGS + asan + ["-c", src, "-o", obj], capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"hipcc failed for {obj}:\n{r.stderr[-4000:]}")
+
+    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+        list(ex.map(lambda u: comp(*u), units))
+    others = [os.path.join(BUILD, o) for _, o, _ in _units() if o[:-2] not in HOST_UNITS]
+    # the driver is host code only: compiled by the ROCm clang as plain C++
+    drv = os.path.join(PKG, os.pardir, "tests", "asan", "host_checks.cpp")
+    drv_o = os.path.join(ASAN_DIR, "host_checks.o")
+    clang = os.path.join(os.path.dirname(os.path.realpath(HIPCC)), os.pardir, "lib", "llvm", "bin", "clang++")
+    r = subprocess.run([clang, "-O1", "-g", "-std=c++17", "-fsanitize=address", "-fno-omit-frame-pointer", "-c",
+                        drv, "-o", drv_o], capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"compiling the host checks failed:\n{r.stderr[-4000:]}")
+    cmd = [HIPCC, f"--offload-arch={ARCH}"] + asan + [drv_o] + [o for _, o in units] + others + ["-o", ASAN_EXE]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"linking the host checks failed:\n{r.stderr[-4000:]}")
+    return ASAN_EXE
+
+
 if __name__ == "__main__":
     import sys
-    build(remarks="--remarks" in sys.argv, incremental="--incremental" in sys.argv)
+    if "--asan" in sys.argv:
+        print(build_asan())
+    else:
+        build(remarks="--remarks" in sys.argv, incremental="--incremental" in sys.argv)
