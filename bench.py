@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--no-pairs", action="store_true", help="skip the summary of the other pairs")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched N-way and the learned-tuner legs")
+    ap.add_argument("--tuner-samples", default="",
+                    help="also save the learned-tuner leg's profiled samples to this .npz file")
     ap.add_argument("--no-cold", action="store_true",
                     help="skip the scrubbed-cache repeats (profiled runs: every traced launch is then a warm one)")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -465,7 +467,7 @@ def batch_leg(reps, log=sys.stderr):
     return out
 
 
-def learned_tuner_leg(log=sys.stderr):
+def learned_tuner_leg(log=sys.stderr, save=""):
     """The learned tuner at its workload's shape: 40 random pairs of the five
     data kernels (2^16..2^26 elements, seed 2), every candidate of the
     exhaustive search profiled (85 per pair), the cost model trained on the
@@ -481,6 +483,10 @@ def learned_tuner_leg(log=sys.stderr):
     pairs = LT.draw_pairs(40, seed=2, kmin=16, kmax=26, kinds=LT.DATA_KINDS)
     data = LT.collect(pairs, reps=10, seed=2, log=open(os.devnull, "w"))
     t1 = time.time()
+    if save:
+        import numpy as np
+        np.savez(save, X=data["X"], y=data["y"], pair=data["pair"], cand=data["cand"],
+                 cands=np.array(data["cands"]), pairs=np.array(pairs))
     res = LT.evaluate(data, folds=4, per_pair=50, topk=3, epochs=500)
     torch.cuda.empty_cache()
     keep = ("regret_mlp_mean", "regret_mlp_max", "regret_naive_mean", "regret_r0_mean", "regret_random_mean",
@@ -600,7 +606,7 @@ def main():
         print("batch leg", file=sys.stderr, flush=True)
         res["batch"] = batch_leg(max(5, min(a.steps, 20)))
         print("learned tuner leg", file=sys.stderr, flush=True)
-        res["learned_tuner"] = learned_tuner_leg()
+        res["learned_tuner"] = learned_tuner_leg(save=a.tuner_samples)
     print(json.dumps(res), flush=True)
     return 0
 

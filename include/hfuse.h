@@ -243,8 +243,9 @@ enum {
   HF_TUNE_PAPER = 1,      /* Main search of Sec. III-B: d0 = 1024, d1 = 128, 256, ..., 896; each
                              partition profiled without and with the bound r0       */
   HF_TUNE_NAIVE = 2,      /* even split, no bound, no search (Sec. IV-A "Naive")     */
-  HF_TUNE_MLP = 3,        /* learned cost model ranks all candidates; only the top-k
-                             are profiled                                           */
+  HF_TUNE_MLP = 3,        /* learned cost model ranks all candidates; only the k
+                             best-ranked with pairwise distinct (split, block) are
+                             profiled                                               */
   HF_TUNE_EXHAUSTIVE_GRID = 4 /* EXHAUSTIVE, then the launch grid: the three best
                              configurations profiled again at 2, 4 and 8 times the
                              occupancy grid (skipped for a configuration whose
@@ -312,6 +313,16 @@ int hf_register_bound(int d1, int d2, int vgpr_a, int vgpr_b, int lds_fused);
 /* Allocates the model for d_in features: He-uniform weights from `seed`
  * (splitmix64), zero biases, identity feature standardisation. */
 int hf_mlp_init(int d_in, uint64_t seed);
+/* The same with `members` networks (1..HF_MLP_MAX_MEMBERS), member k drawn
+ * from seed + k: hf_mlp_train trains every member on the same data, and
+ * predictions are the members' mean (an ensemble, which varies less with the
+ * draw of the training pairs than one network).  hf_mlp_get_params,
+ * hf_mlp_set_params, hf_mlp_grad, hf_mlp_step and hf_mlp_adam_reset act on
+ * the first member. */
+#define HF_MLP_MAX_MEMBERS 16
+int hf_mlp_init_ensemble(int d_in, uint64_t seed, int members);
+/* Members of the current model, or HF_ENOMODEL. */
+int hf_mlp_members(void);
 /* Number of parameters of the current model, or HF_ENOMODEL. */
 int hf_mlp_num_params(void);
 /* Copies the flat parameter vector (layout W1[d][64] b1 W2[64][64] b2 W3 b3
@@ -327,10 +338,12 @@ int hf_mlp_step(const float* X, const float* y, int n, float lr, float* loss_out
 /* Zeroes Adam's moments and step count. */
 int hf_mlp_adam_reset(void);
 /* Standardises raw X[n][d] and y[n] with their own mean and deviation (kept in
- * the model), resets Adam and runs `epochs` full-batch steps; loss_out (may be
- * NULL) receives the standardised training loss after the last step. */
+ * the model), resets Adam and runs `epochs` full-batch steps for every member;
+ * loss_out (may be NULL) receives the members' mean standardised training loss
+ * after the last step. */
 int hf_mlp_train(const float* X, const float* y, int n, int d, int epochs, float lr, float* loss_out);
-/* Predictions for raw X[n][d] in the units of the training targets. */
+/* Predictions for raw X[n][d] in the units of the training targets (the mean
+ * over the members). */
 int hf_mlp_predict(const float* X, int n, float* y_out);
 /* Saves / loads the model (parameters and standardisation) to / from a file. */
 int hf_mlp_save(const char* path);

@@ -58,6 +58,10 @@ struct Im2colArgs {  // patches -> columns, [N][C*kh*kw][Ho*Wo]
   uint32_t lanes_per_unit;  // Ho * Wo4 (vector) or Ho * Wo (scalar)
   uint32_t vec;             // Wo % 4 == 0 and out 16-byte aligned
   FastDiv div_kk, div_row, div_kw;  // div_row: by Wo4 (vector) or Wo
+  uint32_t row3;            // the 3x3 / stride 1 / pad 1 row path (see Im2col)
+  uint32_t nq;              // row path: quads of input rows per channel, ceil(H / 4)
+  uint32_t row_units;       // row path: N * C * nq
+  FastDiv div_nq;
 };
 
 struct UpArgs {  // bilinear upsampling by integer factor s, half-pixel centres
@@ -81,6 +85,10 @@ struct PoolArgs {  // max pooling with the winner's flat index
   uint32_t total;  // N*C*Ho*Wo outputs
   uint32_t units;  // ceil(total / Maxpool::kUnit)
   FastDiv div_plane, div_wo;  // by Ho*Wo and by Wo
+  uint32_t row3;       // the 3x3 / stride 2 / pad 1 row path (see Maxpool)
+  uint32_t nq;         // row path: quads of output rows per plane, ceil(Ho / 4)
+  uint32_t row_units;  // row path: planes * nq
+  FastDiv div_nq;
 };
 
 struct ShaArgs {  // SHA-256d and BLAKE2b over header || nonce
@@ -373,6 +381,14 @@ struct BnStats {
 // ================================================================== int_mix
 // Integer mixing loop standing in for the compute-bound hash kernels: per element
 // R rounds of  x ^= x<<13; x ^= x>>17; x ^= x<<5; x = x*2654435761 + r  (mod 2^32).
+//
+// A lane's grid-stride walk goes in steps of up to four uint4 vectors (sixteen
+// independent chains): four while at least four remain, then one step of the
+// remaining one to three.  The vector-memory counter retires in order, so the
+// wait for a step's loads also waits for the previous step's stores: each step
+// exposes one load and one store latency, and four vectors per step divide the
+// number of steps, and of exposed latencies, by four without computing any
+// vector twice.
 struct IntMix {
   static constexpr uint32_t lds_words(int) { return 0; }
 
@@ -383,6 +399,26 @@ struct IntMix {
     return x * 2654435761u + r;
   }
 
+  // vectors i, i + stride, ..., i + (K-1)*stride, all in range
+  template <uint32_t K>
+  __device__ static __forceinline__ void step(const uint4* in4, uint4* out4, uint32_t i, uint32_t stride,
+                                              uint32_t R) {
+    uint4 v[K];
+#pragma unroll
+    for (uint32_t k = 0; k < K; ++k) v[k] = in4[i + k * stride];
+    for (uint32_t r = 0; r < R; ++r) {
+#pragma unroll
+      for (uint32_t k = 0; k < K; ++k) {
+        v[k].x = round1(v[k].x, r);
+        v[k].y = round1(v[k].y, r);
+        v[k].z = round1(v[k].z, r);
+        v[k].w = round1(v[k].w, r);
+      }
+    }
+#pragma unroll
+    for (uint32_t k = 0; k < K; ++k) out4[i + k * stride] = v[k];
+  }
+
   template <class Bar>
   __device__ static void run(const DevTask& dt, const Part& p, Bar&, uint32_t*) {
     const MixArgs& a = dt.mix;
@@ -391,15 +427,14 @@ struct IntMix {
     const uint32_t R = (uint32_t)a.rounds;
     const uint4* in4 = reinterpret_cast<const uint4*>(a.in);
     uint4* out4 = reinterpret_cast<uint4*>(a.out);
-    for (uint32_t i = gl; i < a.n4; i += stride) {
-      uint4 v = in4[i];
-      for (uint32_t r = 0; r < R; ++r) {  // four independent chains per lane
-        v.x = round1(v.x, r);
-        v.y = round1(v.y, r);
-        v.z = round1(v.z, r);
-        v.w = round1(v.w, r);
-      }
-      out4[i] = v;
+    if (gl < a.n4) {
+      // vectors left for this lane, i = gl, gl + stride, ...
+      uint32_t left = (a.n4 - gl + stride - 1u) / stride;
+      uint32_t i = gl;
+      for (; left >= 4u; left -= 4u, i += 4u * stride) step<4>(in4, out4, i, stride, R);
+      if (left == 3u) step<3>(in4, out4, i, stride, R);
+      else if (left == 2u) step<2>(in4, out4, i, stride, R);
+      else if (left == 1u) step<1>(in4, out4, i, stride, R);
     }
     for (uint32_t i = 4u * a.n4 + gl; i < a.n; i += stride) {
       uint32_t x = a.in[i];
@@ -435,6 +470,12 @@ struct LdsHist {
     count_byte(mine, (w >> 16) & 0xFFu);
     count_byte(mine, w >> 24);
   }
+  __device__ static __forceinline__ void count_vec(uint32_t* mine, const uint4& q) {
+    count_word(mine, q.x);
+    count_word(mine, q.y);
+    count_word(mine, q.z);
+    count_word(mine, q.w);
+  }
 
   template <class Bar>
   __device__ static void run(const DevTask& dt, const Part& p, Bar& bar, uint32_t* lds) {
@@ -447,12 +488,23 @@ struct LdsHist {
     const uint32_t gl = p.wg * p.nlanes + p.lane;
     const uint32_t stride = p.nwg * p.nlanes;
     const uint4* v16 = reinterpret_cast<const uint4*>(a.in + a.head);
-    for (uint32_t i = gl; i < a.n16; i += stride) {
-      const uint4 q = v16[i];
-      count_word(mine, q.x);
-      count_word(mine, q.y);
-      count_word(mine, q.z);
-      count_word(mine, q.w);
+    // Two vectors per step, and the next step's two requested before this
+    // step's atomics, so up to four 16-byte loads per lane are in flight:
+    // inside a fused kernel the interval may have only a few wavefronts per
+    // CU, and their loads alone must keep the input streaming.  The loop has
+    // no stores, so each wait covers only the loads it needs.
+    if (gl < a.n16) {
+      const uint32_t last = a.n16 - 1u;
+      uint4 q0 = v16[gl], q1 = v16[min(gl + stride, last)];
+      uint32_t i = gl;
+      for (; i + stride < a.n16; i += 2u * stride) {
+        const uint4 p0 = v16[min(i + 2u * stride, last)], p1 = v16[min(i + 3u * stride, last)];
+        count_vec(mine, q0);
+        count_vec(mine, q1);
+        q0 = p0;
+        q1 = p1;
+      }
+      if (i < a.n16) count_vec(mine, q0);  // the last vector of an odd count
     }
     if (gl < a.head) count_byte(mine, a.in[gl]);
     for (uint32_t i = a.tail_start + gl; i < a.n; i += stride) count_byte(mine, a.in[i]);
@@ -487,13 +539,72 @@ struct LdsHist {
 // store instruction covers whole aligned cache lines.  Kernel offsets kk are the
 // fastest-varying unit index, so the kh*kw planes that read one input plane run
 // next to each other and find it in cache.
+//
+// Row path (3x3 kernel, stride 1, pad 1, W % 4 == 0, W <= 64, 16-byte aligned
+// input and output): with stride 1 the nine output planes of an input channel
+// are its rows shifted by -1, 0, +1 rows and columns with zero fill, so the
+// input is read once, in aligned float4, instead of once per output plane.  A
+// unit is four input rows of one channel, one row per 16-lane DPP row of the
+// wavefront (lane 16q + c holds columns 4c..4c+3 of row q; lanes with
+// c >= W/4 hold zeros).  The column shifts take the neighbouring lane's edge
+// element with a DPP row shift whose out-of-row source reads zero, which is
+// exactly the zero padding; each input row is stored to its three output rows
+// in each of the three column-shifted planes.  Each store instruction writes
+// four consecutive output rows of one plane, 64*W contiguous bytes.
 struct Im2col {
   static constexpr uint32_t lds_words(int) { return 0; }
+
+  __device__ static __forceinline__ void zero4(float* p) { store_nt4(p, 0.f, 0.f, 0.f, 0.f); }
+
+  __device__ static void run_rows(const Im2colArgs& a, const Part& p, uint32_t lane) {
+    const uint32_t nw = p.nwg * p.nwaves;
+    const uint32_t gw = p.wg * p.nwaves + p.wave;
+    const uint32_t q = a.row_units / nw, r = a.row_units - q * nw;
+    const uint32_t ubeg = gw * q + min(gw, r);
+    const uint32_t uend = ubeg + q + (gw < r ? 1u : 0u);
+    const uint32_t W = a.W, H = a.H, HW = H * W;
+    const uint32_t qrow = lane >> 4, c4 = lane & 15u;
+    const bool colok = c4 < W / 4u;
+    for (uint32_t u = ubeg; u < uend; ++u) {
+      const uint32_t nc = fdiv(u, a.div_nq);
+      const uint32_t ih = 4u * (u - nc * a.nq) + qrow;
+      const bool ok = colok && ih < H;
+      float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (ok) x = *reinterpret_cast<const float4*>(a.x + (size_t)nc * HW + ih * W + 4u * c4);
+      // every lane takes part in the shifts: row_shr:1 and row_shl:1, zero
+      // from outside the 16-lane row
+      const float left = dpp_f32<0x111>(x.w);
+      const float right = dpp_f32<0x101>(x.x);
+      float* planes = a.out + (size_t)nc * 9u * HW + 4u * c4;
+      if (ok) {
+#pragma unroll
+        for (uint32_t i = 0; i < 3; ++i) {
+          const uint32_t oh = ih + 1u - i;  // wraps past H when ih + 1 < i
+          if (oh < H) {
+            float* d = planes + (size_t)(3u * i) * HW + oh * W;
+            store_nt4(d, left, x.x, x.y, x.z);
+            store_nt4(d + HW, x.x, x.y, x.z, x.w);
+            store_nt4(d + 2u * HW, x.y, x.z, x.w, right);
+          }
+        }
+      }
+      // the rows no input row reaches: row 0 of the planes that look one row
+      // up, row H-1 of the planes that look one row down
+      if (colok && ih == 0u)
+        for (uint32_t j = 0; j < 3; ++j) zero4(planes + (size_t)j * HW);
+      if (colok && ih == H - 1u)
+        for (uint32_t j = 0; j < 3; ++j) zero4(planes + (size_t)(6u + j) * HW + (H - 1u) * W);
+    }
+  }
 
   template <class Bar>
   __device__ static void run(const DevTask& dt, const Part& p, Bar&, uint32_t*) {
     const Im2colArgs& a = dt.im2col;
     const uint32_t lane = lane_id();
+    if (a.row3) {
+      run_rows(a, p, lane);
+      return;
+    }
     const uint32_t nw = p.nwg * p.nwaves;
     const uint32_t HW = a.H * a.W;
     const uint32_t plane = a.Ho * a.Wo;
@@ -620,10 +731,80 @@ struct Upsample {
 // same element, never between two other elements, so under the scan rule (a
 // later element wins only if greater or NaN) the winner and its index are
 // exactly those of the unclamped scan.  All loads are therefore unconditional.
+//
+// Row path (3x3 window, stride 2, pad 1, W % 8 == 0, W <= 128, 16-byte
+// aligned buffers): a unit is four output rows of one plane, one per 16-lane
+// DPP row of the wavefront.  Lane 16q + c computes outputs 4c..4c+3 of its
+// row, whose windows span input columns 8c-1 .. 8c+7 of three input rows:
+// columns 8c..8c+7 are two aligned float4 per row, and column 8c-1 is the left
+// neighbour lane's last element, taken with a DPP row shift (at c = 0 the
+// column clamps to 0, as in the general path).  Rows clamp the same way.
+// Each window is scanned in the general path's order, and values and indices
+// are stored as float4 / int4, four output rows per store instruction.
 struct Maxpool {
   static constexpr uint32_t kPer = 2;
   static constexpr uint32_t kUnit = 64 * kPer;
   static constexpr uint32_t lds_words(int) { return 0; }
+
+  __device__ static __forceinline__ void take(float v, int32_t e, bool first, float& best, int32_t& at) {
+    if (first || v > best || __builtin_isnan(v)) {
+      best = v;
+      at = e;
+    }
+  }
+
+  __device__ static void run_rows(const PoolArgs& a, const Part& p, uint32_t lane) {
+    const uint32_t nw = p.nwg * p.nwaves;
+    const uint32_t gw = p.wg * p.nwaves + p.wave;
+    const uint32_t q = a.row_units / nw, r = a.row_units - q * nw;
+    const uint32_t ubeg = gw * q + min(gw, r);
+    const uint32_t uend = ubeg + q + (gw < r ? 1u : 0u);
+    const uint32_t W = a.W, Wo4 = a.Wo / 4u;
+    const uint32_t qrow = lane >> 4, c = lane & 15u;
+    const uint32_t cc = min(c, Wo4 - 1u);  // lanes past the row load in bounds and store nothing
+    for (uint32_t u = ubeg; u < uend; ++u) {
+      const uint32_t plane = fdiv(u, a.div_nq);
+      const uint32_t oh = 4u * (u - plane * a.nq) + qrow;
+      const bool ok = c < Wo4 && oh < a.Ho;
+      const uint32_t ohc = min(oh, a.Ho - 1u);
+      const float* img = a.x + (size_t)plane * a.H * W;
+      float best[4];
+      int32_t at[4];
+#pragma unroll
+      for (uint32_t i = 0; i < 3; ++i) {
+        const int32_t h = clampi((int32_t)(2u * ohc + i) - 1, (int32_t)a.H - 1);
+        const float* rowp = img + (size_t)h * W + 8u * cc;
+        const float4 A = *reinterpret_cast<const float4*>(rowp);
+        const float4 B = *reinterpret_cast<const float4*>(rowp + 4);
+        const float lft = dpp_f32<0x111>(B.w);  // column 8c - 1 from lane c - 1 of this row
+        const int32_t e0 = h * (int32_t)W + 8 * (int32_t)cc;
+        const float L = cc == 0u ? A.x : lft;
+        const int32_t eL = cc == 0u ? e0 : e0 - 1;
+        const bool f = i == 0;
+        take(L, eL, f, best[0], at[0]);
+        take(A.x, e0, false, best[0], at[0]);
+        take(A.y, e0 + 1, false, best[0], at[0]);
+        take(A.y, e0 + 1, f, best[1], at[1]);
+        take(A.z, e0 + 2, false, best[1], at[1]);
+        take(A.w, e0 + 3, false, best[1], at[1]);
+        take(A.w, e0 + 3, f, best[2], at[2]);
+        take(B.x, e0 + 4, false, best[2], at[2]);
+        take(B.y, e0 + 5, false, best[2], at[2]);
+        take(B.y, e0 + 5, f, best[3], at[3]);
+        take(B.z, e0 + 6, false, best[3], at[3]);
+        take(B.w, e0 + 7, false, best[3], at[3]);
+      }
+      if (ok) {
+        const size_t o = (size_t)plane * a.Ho * a.Wo + (size_t)oh * a.Wo + 4u * c;
+        store_nt4(a.out + o, best[0], best[1], best[2], best[3]);
+        if (a.idx) {
+          typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+          const i32x4 v = {at[0], at[1], at[2], at[3]};
+          __builtin_nontemporal_store(v, reinterpret_cast<i32x4*>(a.idx + o));
+        }
+      }
+    }
+  }
 
   __device__ static __forceinline__ int32_t clampi(int32_t v, int32_t hi) { return min(max(v, 0), hi); }
 
@@ -678,6 +859,10 @@ struct Maxpool {
   __device__ static void run(const DevTask& dt, const Part& p, Bar&, uint32_t*) {
     const PoolArgs& a = dt.pool;
     const uint32_t lane = lane_id();
+    if (a.row3) {
+      run_rows(a, p, lane);
+      return;
+    }
     const uint32_t nw = p.nwg * p.nwaves;
     const uint32_t gw = p.wg * p.nwaves + p.wave;
     const uint32_t q = a.units / nw, r = a.units - q * nw;

@@ -110,9 +110,14 @@ __global__ void __launch_bounds__(256) k_adam(float* __restrict__ p, const float
 }
 
 // ------------------------------------------------------------------ model state
+// An ensemble of `members` networks of the same shape, trained one after the
+// other on the same standardised data from different initial weights; the
+// prediction is the mean of the members' predictions.  p/m/v point at the
+// active member's slice of pall/mall/vall (use_member).
 struct MlpModel {
-  int d = 0, np = 0, cap_n = 0, t = 0;
+  int d = 0, np = 0, cap_n = 0, t = 0, members = 1;
   bool trained = false;
+  float *pall = nullptr, *mall = nullptr, *vall = nullptr;
   float *p = nullptr, *m = nullptr, *v = nullptr, *g = nullptr;
   // workspace
   float *X = nullptr, *y = nullptr, *Z1 = nullptr, *H1 = nullptr, *Z2 = nullptr, *H2 = nullptr;
@@ -136,13 +141,19 @@ static void mlp_free_ws(MlpModel* M) {
   M->cap_n = 0;
 }
 
+static void use_member(MlpModel* M, int k) {
+  M->p = M->pall + (size_t)k * M->np;
+  M->m = M->mall + (size_t)k * M->np;
+  M->v = M->vall + (size_t)k * M->np;
+}
+
 void mlp_free() {
   if (!g_model) return;
   int cur = 0;
   (void)hipGetDevice(&cur);
   (void)hipSetDevice(g_model_dev);
   mlp_free_ws(g_model);
-  float** ps[] = {&g_model->p, &g_model->m, &g_model->v, &g_model->g};
+  float** ps[] = {&g_model->pall, &g_model->mall, &g_model->vall, &g_model->g};
   for (float** q : ps)
     if (*q) (void)hipFree(*q);
   delete g_model;
@@ -440,15 +451,23 @@ static void standardise(const MlpModel* M, const float* X, int n, std::vector<fl
       (*out)[(size_t)i * M->d + k] = (X[(size_t)i * M->d + k] - M->mu[k]) / M->sd[k];
 }
 
+// Mean of the members' predictions, in the units of the training targets.
 static int predict(MlpModel* M, const float* X, int n, float* y, hipStream_t st) {
   int rc;
   if ((rc = ensure_ws(M, n)) != HF_OK) return rc;
-  std::vector<float> xs;
+  std::vector<float> xs, yk(n);
   standardise(M, X, n, &xs);
   if ((rc = upload(M->X, xs.data(), xs.size(), st)) != HF_OK) return rc;
-  if ((rc = forward(M, n, st)) != HF_OK) return rc;
-  if ((rc = download(y, M->yh, n, st)) != HF_OK) return rc;
-  for (int i = 0; i < n; ++i) y[i] = y[i] * M->ysd + M->ymu;
+  std::vector<double> acc(n, 0.0);
+  for (int k = 0; k < M->members; ++k) {
+    use_member(M, k);
+    if ((rc = forward(M, n, st)) != HF_OK) break;
+    if ((rc = download(yk.data(), M->yh, n, st)) != HF_OK) break;
+    for (int i = 0; i < n; ++i) acc[i] += yk[i];
+  }
+  use_member(M, 0);
+  if (rc != HF_OK) return rc;
+  for (int i = 0; i < n; ++i) y[i] = (float)(acc[i] / M->members) * M->ysd + M->ymu;
   return HF_OK;
 }
 
@@ -474,8 +493,8 @@ using namespace hf;
 
 extern "C" {
 
-int hf_mlp_init(int d_in, uint64_t seed) {
-  if (d_in < 1 || d_in > 4096) return HF_EINVAL;
+int hf_mlp_init_ensemble(int d_in, uint64_t seed, int members) {
+  if (d_in < 1 || d_in > 4096 || members < 1 || members > HF_MLP_MAX_MEMBERS) return HF_EINVAL;
   int rc;
   DeviceState* s = device_state(&rc);
   if (!s) return rc;
@@ -483,33 +502,50 @@ int hf_mlp_init(int d_in, uint64_t seed) {
   MlpModel* M = new MlpModel();
   M->d = d_in;
   M->np = nparams(d_in);
-  if ((rc = alloc_f(&M->p, M->np)) || (rc = alloc_f(&M->m, M->np)) || (rc = alloc_f(&M->v, M->np)) ||
+  M->members = members;
+  const size_t all = (size_t)members * M->np;
+  if ((rc = alloc_f(&M->pall, all)) || (rc = alloc_f(&M->mall, all)) || (rc = alloc_f(&M->vall, all)) ||
       (rc = alloc_f(&M->g, M->np))) {
+    float** ps[] = {&M->pall, &M->mall, &M->vall, &M->g};
+    for (float** q : ps)
+      if (*q) (void)hipFree(*q);
     delete M;
     return rc;
   }
-  // He-uniform weights U(-sqrt(6/fan_in), +sqrt(6/fan_in)), zero biases
-  std::vector<float> host(M->np, 0.f);
+  use_member(M, 0);
+  // He-uniform weights U(-sqrt(6/fan_in), +sqrt(6/fan_in)), zero biases;
+  // member k draws from the splitmix64 stream seeded with seed + k
+  std::vector<float> host(all, 0.f);
   const int dims[5] = {d_in, kHid, kHid, kHid, 1};
-  uint64_t st = seed;
-  size_t o = 0;
-  for (int l = 0; l < 4; ++l) {
-    const double lim = std::sqrt(6.0 / dims[l]);
-    for (int i = 0; i < dims[l] * dims[l + 1]; ++i) {
-      const double u = (double)(splitmix64(st) >> 11) * (1.0 / 9007199254740992.0);
-      host[o++] = (float)((2.0 * u - 1.0) * lim);
+  for (int k = 0; k < members; ++k) {
+    uint64_t st = seed + (uint64_t)k;
+    size_t o = (size_t)k * M->np;
+    for (int l = 0; l < 4; ++l) {
+      const double lim = std::sqrt(6.0 / dims[l]);
+      for (int i = 0; i < dims[l] * dims[l + 1]; ++i) {
+        const double u = (double)(splitmix64(st) >> 11) * (1.0 / 9007199254740992.0);
+        host[o++] = (float)((2.0 * u - 1.0) * lim);
+      }
+      o += dims[l + 1];
     }
-    o += dims[l + 1];
   }
   M->mu.assign(d_in, 0.f);
   M->sd.assign(d_in, 1.f);
   g_model = M;
   g_model_dev = s->device;
-  hipError_t e = hipMemcpy(M->p, host.data(), host.size() * sizeof(float), hipMemcpyHostToDevice);
+  hipError_t e = hipMemcpy(M->pall, host.data(), host.size() * sizeof(float), hipMemcpyHostToDevice);
   if (e != hipSuccess) return record_hip(e);
-  if ((e = hipMemset(M->m, 0, M->np * sizeof(float))) != hipSuccess) return record_hip(e);
-  if ((e = hipMemset(M->v, 0, M->np * sizeof(float))) != hipSuccess) return record_hip(e);
+  if ((e = hipMemset(M->mall, 0, all * sizeof(float))) != hipSuccess) return record_hip(e);
+  if ((e = hipMemset(M->vall, 0, all * sizeof(float))) != hipSuccess) return record_hip(e);
   return HF_OK;
+}
+
+int hf_mlp_init(int d_in, uint64_t seed) { return hf_mlp_init_ensemble(d_in, seed, 1); }
+
+int hf_mlp_members(void) {
+  MlpModel* M = nullptr;
+  int rc = model(&M);
+  return rc != HF_OK ? rc : M->members;
 }
 
 int hf_mlp_num_params(void) {
@@ -599,16 +635,32 @@ int hf_mlp_train(const float* X, const float* y, int n, int d, int epochs, float
   std::vector<float> xs, ys(n);
   standardise(M, X, n, &xs);
   for (int i = 0; i < n; ++i) ys[i] = (y[i] - M->ymu) / M->ysd;
-  if ((rc = hf_mlp_adam_reset()) != HF_OK) return rc;
   if ((rc = ensure_ws(M, n)) != HF_OK) return rc;
   if ((rc = upload(M->X, xs.data(), xs.size(), nullptr)) || (rc = upload(M->y, ys.data(), n, nullptr))) return rc;
-  for (int ep = 0; ep < epochs; ++ep)
-    if ((rc = forward(M, n, nullptr)) || (rc = backward(M, n, nullptr)) || (rc = adam(M, lr, nullptr))) return rc;
-  // loss of the final parameters
-  if ((rc = forward(M, n, nullptr)) || (rc = backward(M, n, nullptr))) return rc;
-  float l = 0.f;
-  if ((rc = download(&l, M->loss, 1, nullptr)) != HF_OK) return rc;
-  if (loss_out) *loss_out = l;
+  // every member from its own initial weights, on the same data
+  double lsum = 0.0;
+  for (int k = 0; k < M->members; ++k) {
+    use_member(M, k);
+    M->t = 0;
+    hipError_t e;
+    if ((e = hipMemset(M->m, 0, M->np * sizeof(float))) != hipSuccess ||
+        (e = hipMemset(M->v, 0, M->np * sizeof(float))) != hipSuccess) {
+      use_member(M, 0);
+      return record_hip(e);
+    }
+    for (int ep = 0; ep < epochs && rc == HF_OK; ++ep)
+      if ((rc = forward(M, n, nullptr)) || (rc = backward(M, n, nullptr)) || (rc = adam(M, lr, nullptr))) break;
+    // loss of the member's final parameters
+    if (rc == HF_OK && ((rc = forward(M, n, nullptr)) == HF_OK) && ((rc = backward(M, n, nullptr)) == HF_OK)) {
+      float l = 0.f;
+      rc = download(&l, M->loss, 1, nullptr);
+      lsum += l;
+    }
+    if (rc != HF_OK) break;
+  }
+  use_member(M, 0);
+  if (rc != HF_OK) return rc;
+  if (loss_out) *loss_out = (float)(lsum / M->members);
   M->trained = true;
   return HF_OK;
 }
@@ -626,17 +678,18 @@ int hf_mlp_save(const char* path) {
   int rc = model(&M);
   if (rc != HF_OK) return rc;
   if (!path) return HF_EINVAL;
-  std::vector<float> p(M->np);
-  if ((rc = download(p.data(), M->p, M->np, nullptr)) != HF_OK) return rc;
+  const size_t all = (size_t)M->members * M->np;
+  std::vector<float> p(all);
+  if ((rc = download(p.data(), M->pall, all, nullptr)) != HF_OK) return rc;
   FILE* f = std::fopen(path, "wb");
   if (!f) return HF_EINVAL;
-  const char magic[8] = {'H', 'F', 'M', 'L', 'P', '1', 0, 0};
-  const int32_t hdr[3] = {M->d, M->np, M->trained ? 1 : 0};
-  bool ok = std::fwrite(magic, 1, 8, f) == 8 && std::fwrite(hdr, 4, 3, f) == 3 &&
+  const char magic[8] = {'H', 'F', 'M', 'L', 'P', '2', 0, 0};
+  const int32_t hdr[4] = {M->d, M->np, M->trained ? 1 : 0, M->members};
+  bool ok = std::fwrite(magic, 1, 8, f) == 8 && std::fwrite(hdr, 4, 4, f) == 4 &&
             std::fwrite(&M->ymu, 4, 1, f) == 1 && std::fwrite(&M->ysd, 4, 1, f) == 1 &&
             std::fwrite(M->mu.data(), 4, M->d, f) == (size_t)M->d &&
             std::fwrite(M->sd.data(), 4, M->d, f) == (size_t)M->d &&
-            std::fwrite(p.data(), 4, M->np, f) == (size_t)M->np;
+            std::fwrite(p.data(), 4, all, f) == all;
   ok = (std::fclose(f) == 0) && ok;
   return ok ? HF_OK : HF_EINVAL;
 }
@@ -646,23 +699,27 @@ int hf_mlp_load(const char* path) {
   FILE* f = std::fopen(path, "rb");
   if (!f) return HF_EINVAL;
   char magic[8];
-  int32_t hdr[3];
-  bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, "HFMLP1", 6) == 0 &&
-            std::fread(hdr, 4, 3, f) == 3 && hdr[0] >= 1 && hdr[0] <= 4096 && hdr[1] == nparams(hdr[0]);
+  int32_t hdr[4];
+  bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, "HFMLP2", 6) == 0 &&
+            std::fread(hdr, 4, 4, f) == 4 && hdr[0] >= 1 && hdr[0] <= 4096 && hdr[1] == nparams(hdr[0]) &&
+            hdr[3] >= 1 && hdr[3] <= HF_MLP_MAX_MEMBERS;
   if (!ok) {
     std::fclose(f);
     return HF_EINVAL;
   }
   float ymu = 0, ysd = 1;
-  std::vector<float> mu(hdr[0]), sd(hdr[0]), p(hdr[1]);
+  const size_t all = (size_t)hdr[3] * hdr[1];
+  std::vector<float> mu(hdr[0]), sd(hdr[0]), p(all);
   ok = std::fread(&ymu, 4, 1, f) == 1 && std::fread(&ysd, 4, 1, f) == 1 &&
        std::fread(mu.data(), 4, hdr[0], f) == (size_t)hdr[0] && std::fread(sd.data(), 4, hdr[0], f) == (size_t)hdr[0] &&
-       std::fread(p.data(), 4, hdr[1], f) == (size_t)hdr[1];
+       std::fread(p.data(), 4, all, f) == all;
   std::fclose(f);
   if (!ok) return HF_EINVAL;
-  int rc = hf_mlp_init(hdr[0], 0);
+  int rc = hf_mlp_init_ensemble(hdr[0], 0, hdr[3]);
   if (rc != HF_OK) return rc;
-  if ((rc = hf_mlp_set_params(p.data(), hdr[1])) != HF_OK) return rc;
+  if ((rc = upload(g_model->pall, p.data(), all, nullptr)) != HF_OK) return rc;
+  hipError_t e = hipStreamSynchronize(nullptr);
+  if (e != hipSuccess) return record_hip(e);
   g_model->mu = mu;
   g_model->sd = sd;
   g_model->ymu = ymu;

@@ -342,6 +342,11 @@ int prepare(const hf_task* t, void* scratch, DevTask* dt) {
       a.div_kk = make_fastdiv(a.KK);
       a.div_row = make_fastdiv(rowlen);
       a.div_kw = make_fastdiv(kw);
+      a.row3 = kh == 3 && kw == 3 && s == 1 && p == 1 && a.W % 4u == 0u && a.W <= 64u &&
+               aligned(t->in, 16) && aligned(t->out0, 16);
+      a.nq = (a.H + 3u) / 4u;
+      a.row_units = (uint32_t)t->n * a.C * a.nq;
+      a.div_nq = make_fastdiv(a.nq);
       return HF_OK;
     }
     case HF_UPSAMPLE: {
@@ -381,6 +386,11 @@ int prepare(const hf_task* t, void* scratch, DevTask* dt) {
       a.units = (a.total + Maxpool::kUnit - 1u) / Maxpool::kUnit;
       a.div_plane = make_fastdiv(a.Ho * a.Wo);
       a.div_wo = make_fastdiv(a.Wo);
+      a.row3 = a.kh == 3u && a.kw == 3u && a.s == 2u && a.p == 1u && a.W % 8u == 0u && a.W <= 128u &&
+               aligned(t->in, 16) && aligned(t->out0, 16) && aligned(t->out1, 16);
+      a.nq = (a.Ho + 3u) / 4u;
+      a.row_units = (uint32_t)t->n * (uint32_t)t->c * a.nq;
+      a.div_nq = make_fastdiv(a.nq);
       return HF_OK;
     }
     case HF_SHA256D:
@@ -415,9 +425,9 @@ int64_t useful_wgs(const hf_task* t, const DevTask& d, int waves) {
     case HF_BN_STATS: units = cdiv(d.bn.total, waves); break;
     case HF_INT_MIX: units = cdiv(d.mix.n4 ? d.mix.n4 : d.mix.n, 64 * waves); break;
     case HF_LDS_HIST: units = cdiv(std::max<uint32_t>(d.hist.n16, 1), 64 * waves); break;
-    case HF_IM2COL: units = cdiv(d.im2col.units, waves); break;
+    case HF_IM2COL: units = cdiv(d.im2col.row3 ? d.im2col.row_units : d.im2col.units, waves); break;
     case HF_UPSAMPLE: units = cdiv(d.up.units, waves); break;
-    case HF_MAXPOOL: units = cdiv(d.pool.units, waves); break;
+    case HF_MAXPOOL: units = cdiv(d.pool.row3 ? d.pool.row_units : d.pool.units, waves); break;
     case HF_SHA256D:
     case HF_BLAKE2B: units = cdiv(d.sha.n, 64 * waves); break;
     case HF_ETHASH: units = cdiv(d.eth.n, EthashLike::kPerWave * waves); break;
@@ -687,7 +697,11 @@ __global__ void __launch_bounds__(256) k_zero_words(uint32_t* __restrict__ p, ui
 // lane, as the int_mix body runs it, from registers only (no memory traffic
 // in the loop), so its rate is what the VALU sustains for this instruction mix.
 __global__ void __launch_bounds__(256) k_int_peak(uint32_t* sink, uint32_t rounds) {
-  uint32_t a = threadIdx.x, b = blockIdx.x, c = threadIdx.x ^ 0x5555u, d = blockIdx.x * 977u + threadIdx.x;
+  // every chain starts from a per-lane value, so all four stay vector
+  // registers (a wave-uniform start would let the compiler run a chain on the
+  // scalar unit)
+  uint32_t a = threadIdx.x, b = threadIdx.x * 977u + blockIdx.x, c = threadIdx.x ^ 0x5555u,
+           d = (threadIdx.x << 8) ^ blockIdx.x;
   for (uint32_t r = 0; r < rounds; ++r) {
     a = IntMix::round1(a, r);
     b = IntMix::round1(b, r);

@@ -175,7 +175,17 @@ int hf_tune(const hf_pair* pr, int method, int block, int topk, void* stream, hf
   FeatCost fcost;
   if (method == HF_TUNE_MLP) {
     if ((rc = mlp_rank(s, pr, cands, st, &order, &fcost)) != HF_OK) return rc;
-    if ((int)order.size() > topk) order.resize(topk);
+    // the k best-ranked candidates with pairwise distinct (split, block): the
+    // VGPR bounds of one (split, block) often time alike, and a profile spent
+    // on a second bound of the same split hedges less than another split
+    std::vector<int> top;
+    for (int i : order) {
+      if ((int)top.size() >= topk) break;
+      bool seen = false;
+      for (int j : top) seen = seen || (cands[j].split_waves == cands[i].split_waves && cands[j].block == cands[i].block);
+      if (!seen) top.push_back(i);
+    }
+    order.swap(top);
   }
 
   float tbest = 0.f;

@@ -99,6 +99,8 @@ SIGNATURES = {
                      ctypes.POINTER(hf_tune_stats)]),
     "hf_register_bound": (_I, [_I, _I, _I, _I, _I]),
     "hf_mlp_init": (_I, [_I, ctypes.c_uint64]),
+    "hf_mlp_init_ensemble": (_I, [_I, ctypes.c_uint64, _I]),
+    "hf_mlp_members": (_I, []),
     "hf_mlp_num_params": (_I, []),
     "hf_mlp_get_params": (_I, [_F, ctypes.c_int64]),
     "hf_mlp_set_params": (_I, [_F, ctypes.c_int64]),
@@ -377,8 +379,16 @@ def _f32(a):
     return a, a.ctypes.data_as(_F)
 
 
-def hf_mlp_init(d_in: int = MLP_FEATURES, seed: int = 0):
-    _check(lib().hf_mlp_init(d_in, seed), "hf_mlp_init")
+def hf_mlp_init(d_in: int = MLP_FEATURES, seed: int = 0, members: int = 1):
+    """A new model of `members` networks (an ensemble when members > 1)."""
+    if members == 1:
+        _check(lib().hf_mlp_init(d_in, seed), "hf_mlp_init")
+    else:
+        _check(lib().hf_mlp_init_ensemble(d_in, seed, members), "hf_mlp_init_ensemble")
+
+
+def hf_mlp_members() -> int:
+    return _check(lib().hf_mlp_members(), "hf_mlp_members")
 
 
 def hf_mlp_num_params() -> int:

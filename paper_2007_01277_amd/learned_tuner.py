@@ -203,6 +203,21 @@ def collect(pairs, reps: int = 10, seed: int = 2, log=sys.stderr, store: str = "
 
 
 SUM_SOLO = H.MLP_FEATURES - 1  # feature index of log2(sum of the best solo times)
+MEMBERS = 5  # networks of the cost model's ensemble
+
+
+def pick_topk(pred, cands, k):
+    """Indices of the k best-predicted candidates with pairwise distinct
+    (split, block), as hf_tune(MLP) picks them."""
+    top, seen = [], set()
+    for i in np.argsort(pred, kind="stable"):
+        key = (cands[i][0], cands[i][1])
+        if key not in seen:
+            top.append(int(i))
+            seen.add(key)
+        if len(top) == k:
+            break
+    return np.array(top)
 PER_KERNEL = len(H.KIND_NAMES) + 7  # features per kernel; the first kernel's come first
 FEATURE_LAUNCHES = 2 * 3 * 6  # featurisation: each kernel alone at three block sizes, six launches each
 TUNE_REPS = 20  # hf_tune's timed launches per candidate (after one untimed launch)
@@ -220,10 +235,12 @@ def featurisation_ms(x) -> float:
 
 
 def evaluate(data, folds: int = 4, per_pair: int = 14, topk: int = 3, epochs: int = 500,
-             lr: float = 1e-3, seed: int = 7, ks=(1, 2, 3, 5, 8, 12)):
-    """Regret of the learned tuner on held-out pairs.  The model is trained on
-    t_rel = log2(T_fused) - log2(t_a + t_b), which removes each pair's scale;
-    the order of its predictions within a pair is what the tuner uses."""
+             lr: float = 1e-3, seed: int = 7, ks=(1, 2, 3, 5, 8, 12), members: int = MEMBERS):
+    """Regret of the learned tuner on held-out pairs.  The model (an ensemble
+    of `members` networks) is trained on t_rel = log2(T_fused) - log2(t_a +
+    t_b), which removes each pair's scale; the order of its predictions within
+    a pair is what the tuner uses, profiling the k best with distinct (split,
+    block) (pick_topk)."""
     X, y, pair, cand = data["X"], data["y"], data["pair"], data["cand"]
     yrel = y - X[:, SUM_SOLO]
     keys = data["cands"]
@@ -243,23 +260,24 @@ def evaluate(data, folds: int = 4, per_pair: int = 14, topk: int = 3, epochs: in
             idx = [i for i in tr if pair[i] == p]
             keep += g.choice(idx, size=min(per_pair, len(idx)), replace=False).tolist()
         keep = np.array(sorted(keep))
-        H.hf_mlp_init(X.shape[1], seed + f)
+        H.hf_mlp_init(X.shape[1], 1000 * (seed + f), members=members)
         train_loss.append(H.hf_mlp_train(X[keep], yrel[keep], epochs=epochs, lr=lr))
         for p in sorted(test):
             idx = np.where(pair == p)[0]
             ty = y[idx]
             pred = H.hf_mlp_predict(X[idx])
-            top = np.argsort(pred, kind="stable")[:topk]
+            ck = [keys[c] for c in cand[idx]]
+            top = pick_topk(pred, ck, topk)
             best = ty.min()
             ka, kb = data["pairs"][p][0], data["pairs"][p][1]
             r0 = r0_config(ka, kb).as_tuple()
             rnd = g.choice(len(idx), size=topk, replace=False)
-            order_p = np.argsort(pred, kind="stable")
             rperm = g.permutation(len(idx))
             rec = {"pair": p, "kinds": [H.KIND_NAMES[ka], H.KIND_NAMES[kb]],
                    "log2_sizes": list(data["pairs"][p][2:]),
                    "best_ms": float(2 ** best),
-                   "regret_mlp_at_k": {int(k): float(2 ** (ty[order_p[:k]].min() - best) - 1) for k in ks},
+                   "regret_mlp_at_k": {int(k): float(2 ** (ty[pick_topk(pred, ck, k)].min() - best) - 1)
+                                       for k in ks},
                    "regret_random_at_k": {int(k): float(2 ** (ty[rperm[:k]].min() - best) - 1) for k in ks},
                    "regret_mlp": float(2 ** (ty[top].min() - best) - 1),
                    "regret_naive": float(2 ** (ty[naive] - best) - 1),

@@ -105,6 +105,39 @@ def test_training_fits_a_smooth_target_and_roundtrips_through_a_file():
     assert np.array_equal(H.hf_mlp_predict(Xt), pred)
 
 
+def test_ensemble_predicts_the_mean_of_its_members():
+    # member k of an ensemble starts from the weights a one-network model
+    # seeded with seed + k has; untrained, the ensemble's prediction is the
+    # mean of those models' predictions (fp32 sums of three terms)
+    X, _ = _data(200, 20)
+    singles = []
+    for k in range(3):
+        H.hf_mlp_init(D, 40 + k)
+        singles.append(H.hf_mlp_predict(X).astype(np.float64))
+    H.hf_mlp_init(D, 40, members=3)
+    assert H.hf_mlp_members() == 3
+    got = H.hf_mlp_predict(X).astype(np.float64)
+    want = np.mean(singles, axis=0)
+    assert np.all(np.abs(got - want) <= 1e-6 * (np.abs(want) + np.max(np.abs(singles), axis=0)))
+
+
+def test_ensemble_trains_and_roundtrips_through_a_file():
+    X, y = _data(2000, 21)
+    H.hf_mlp_init(D, 7, members=4)
+    loss = H.hf_mlp_train(X, y, epochs=300, lr=2e-3)
+    assert loss < 0.2
+    Xt, yt = _data(300, 22)
+    pred = H.hf_mlp_predict(Xt)
+    assert np.corrcoef(pred, yt)[0, 1] > 0.8
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "e.bin")
+        H.hf_mlp_save(path)
+        H.hf_mlp_init(D, 99)
+        H.hf_mlp_load(path)
+    assert H.hf_mlp_members() == 4
+    assert np.array_equal(H.hf_mlp_predict(Xt), pred)
+
+
 def test_learned_tuner_beats_the_untuned_choice():
     """On pairs of the five data kernels (the learned-tuner workload): trains on
     tuner-profiled samples of 75 pairs (14 configurations each) and ranks every

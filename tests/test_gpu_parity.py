@@ -206,22 +206,33 @@ def test_edge_cases_pool_and_hashes():
 
 def test_maxpool_ties_nan_and_clamped_windows():
     """Ties keep the first element, NaN propagates, and windows clipped by the
-    padding match the oracle's scan -- solo and fused, with and without indices."""
+    padding match the oracle's scan -- solo and fused, with and without indices.
+    The width-16 image takes the 3x3/s2/p1 row path; its NaNs sit at the
+    columns a lane takes from its left neighbour (8c - 1) and at column 0."""
     x = inputs.normal_image((2, 3, 13, 10), seed=17)
     x[0, 0] = np.round(x[0, 0])  # many ties
     x[0, 1] = 1.0                # one constant plane: every window ties
     x[1, 2, 4, 5] = np.nan
     x[1, 2, 12, 9] = np.nan      # in the bottom-right window, reached by clamping
     x[1, 0] = -np.inf
+    y = inputs.normal_image((2, 3, 13, 16), seed=18)
+    y[0, 0] = np.round(y[0, 0])
+    y[0, 1] = 1.0
+    y[1, 2, 4, 7] = np.nan
+    y[1, 2, 0, 0] = np.nan
+    y[1, 2, 12, 15] = np.nan
+    y[1, 1, 6, 8] = np.nan
+    y[1, 0] = -np.inf
     other = G.mix_case(4097, 3, seed=17)
-    for k, s, p in [((3, 3), 2, 1), ((2, 2), 1, 1), ((3, 2), 3, 0), ((5, 4), 2, 2)]:
-        for with_idx in (True, False):
-            c = G.pool_case(x.shape, k, s, p, x=x, with_idx=with_idx)
-            print(c.label, with_idx, flush=True)
-            for block in BLOCKS:
-                G.run_and_check(lambda: H.hf_run_solo(c.task, block), [c])
-            pr = H.make_pair(c.task, other.task)
-            G.run_and_check(lambda: H.hf_run_fused(pr, 3, 4, 256), [c, other])
+    for img in (x, y):
+        for k, s, p in [((3, 3), 2, 1), ((2, 2), 1, 1), ((3, 2), 3, 0), ((5, 4), 2, 2)]:
+            for with_idx in (True, False):
+                c = G.pool_case(img.shape, k, s, p, x=img, with_idx=with_idx)
+                print(c.label, with_idx, flush=True)
+                for block in BLOCKS:
+                    G.run_and_check(lambda: H.hf_run_solo(c.task, block), [c])
+                pr = H.make_pair(c.task, other.task)
+                G.run_and_check(lambda: H.hf_run_fused(pr, 3, 4, 256), [c, other])
 
 
 def test_bn_constant_input_exact():
