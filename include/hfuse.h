@@ -378,10 +378,48 @@ int hf_batch_destroy(void* batch);
 int hf_run_batch(const hf_task* tasks, int ntask, const int32_t* group_of_task,
                  const int32_t* waves_of_task, int block, void* stream, float* ms_out);
 /* Schedule tuner of a batch: profiles (median of `reps` launches) the cost-
- * proportional and the even wave split at block 256 and 512; writes the best
- * per-task waves (ntask entries) and block, and its median time. */
+ * proportional and the even wave split at blocks 256, 512 and 1024; writes the
+ * best per-task waves (ntask entries) and block, and its median time. */
 int hf_batch_tune(const hf_task* tasks, int ntask, const int32_t* group_of_task, int reps, void* stream,
                   int32_t* waves_out, int32_t* block_out, float* ms_out);
+
+/* A batch schedule.
+ *   block           workgroup size: 256, 512 or 1024.
+ *   interval_waves  0: the static schedule above (each group runs as one N-way
+ *                   fused virtual workgroup per work item, intervals sized per
+ *                   member, whole-workgroup barriers between items);
+ *                   1, 2, 4, 8 or 16 (dividing block/64): worker intervals --
+ *                   each workgroup is cut into intervals of this many
+ *                   wavefronts, and every interval pulls (task, virtual
+ *                   workgroup) items from the device queue on its own, runs
+ *                   the task's body on its interval (interval barrier, own LDS
+ *                   region) and pulls the next, so the intervals of a
+ *                   workgroup run different kernels side by side with no
+ *                   whole-workgroup barrier between items.  The queue holds
+ *                   the members of each group interleaved item by item.
+ *   item_kb         estimated traffic of one work item, KiB (0: 256): the
+ *                   virtual grid of a task is its traffic over this, capped by
+ *                   the workgroups that find work.
+ *   split_policy    static schedule without waves_of_task: 0 = wavefronts in
+ *                   proportion to each member's estimated cost, 1 = even. */
+typedef struct {
+  int32_t block;
+  int32_t interval_waves;
+  int32_t item_kb;
+  int32_t split_policy;
+} hf_batch_schedule;
+/* hf_batch_create under an explicit schedule (waves_of_task must be NULL for
+ * worker intervals).  HF_EUNSUPPORTED when the schedule's LDS does not fit a
+ * CU (worker intervals with a histogram task need 16 KiB per interval). */
+int hf_batch_create_sched(const hf_task* tasks, int ntask, const int32_t* group_of_task,
+                          const int32_t* waves_of_task, const hf_batch_schedule* sched, void** batch_out);
+/* Schedule search over both kinds of schedule: static (blocks 256/512/1024 x
+ * split policy x items of 128/256/512 KiB) and worker intervals (blocks x
+ * intervals of 1/2/4 wavefronts x items of 64/128/256/512 KiB), every
+ * schedule the batch admits profiled as the median of `reps` launches.
+ * Writes the fastest schedule, its median time and the number profiled. */
+int hf_batch_tune_sched(const hf_task* tasks, int ntask, const int32_t* group_of_task, int reps, void* stream,
+                        hf_batch_schedule* best_out, float* ms_out, int32_t* n_profiled);
 
 /* ---------------------------------------------------------------- microbenchmarks */
 /* Streams `bytes` (multiple of 16) from src to dst: the reference copy kernel

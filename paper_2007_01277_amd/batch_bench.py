@@ -14,7 +14,9 @@ Modes timed (median of `reps` runs, events on the launch stream):
   streams4       round-robin over four streams, forked and joined with events
   graph_solo     a HIP graph of the back-to-back launches (launch cost removed,
                  no fusion)
-  batch          the persistent N-way fused kernel, one launch
+  batch          the persistent N-way fused kernel, one launch, under the
+                 schedule the schedule search picks (static groups or worker
+                 intervals; workgroup size, split, item size)
   batch_graph    the same launch replayed from a captured HIP graph
 
     python -m paper_2007_01277_amd.batch_bench --count 1000 --out batch.json
@@ -183,10 +185,14 @@ def run_modes(w: Workload, groups, reps: int = 10, block=None, waves=None, log=s
     # the tuned schedule of the persistent fused kernel
     if block is None:
         t0 = time.time()
-        waves, block, tms = H.hf_batch_tune(w.tasks, groups, reps=5)
+        sched, tms, nprof = H.hf_batch_tune_sched(w.tasks, groups, reps=5)
         res["tune_s"] = round(time.time() - t0, 3)
-    b = H.Batch(w.tasks, groups, waves, block)
-    res["schedule"] = {"block": block, **b.info()}
+        res["schedules_profiled"] = nprof
+        b = H.Batch(w.tasks, groups, schedule=sched)
+        res["schedule"] = {**sched.as_dict(), **b.info()}
+    else:
+        b = H.Batch(w.tasks, groups, waves, block)
+        res["schedule"] = {"block": block, **b.info()}
     w.clear()
     res["batch_ms"] = timed(lambda: b.run(False))
     res["batch_equal"] = same(ref, w.snapshot())

@@ -126,6 +126,68 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE)
   }
 }
 
+// ------------------------------------------------------------------ worker intervals
+// The second schedule: every workgroup is cut into `nint` intervals of `iw`
+// wavefronts, and each interval is a worker of its own: it pulls a (task,
+// virtual workgroup) item from the device queue, runs that task's body on
+// its interval with its own interval barrier and LDS region, and pulls the
+// next, with no whole-workgroup barrier between items.  The intervals of one
+// workgroup run different kernels side by side whenever consecutive queue
+// entries belong to different tasks -- the queue interleaves the members of
+// each group item by item -- which is horizontal fusion with the pairing of
+// intervals and kernels decided at run time instead of per group.  Every
+// item of a task uses the same interval size, so the bodies' decomposition
+// of the task's work is the same whichever interval runs which item.
+struct BatchDynTables {
+  const DevTask* tasks;        // [ntask]
+  const int32_t* kinds;        // [ntask]
+  const uint32_t* nvwg;        // [ntask] virtual workgroups of each task
+  const uint32_t* item_task;   // [total_items] task of each queue entry
+  const uint32_t* item_vwg;    // [total_items] its virtual workgroup
+  uint32_t* queue;             // [1] pull counter, zero between launches
+  uint32_t total_items;
+  uint32_t iw;                 // wavefronts per interval
+  uint32_t hist_words;         // LDS words of each interval's histogram region (0: none)
+};
+
+template <int BLOCK, bool HASH, int WPE>
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(WPE))) k_batch_dyn(BatchDynTables T) {
+  constexpr uint32_t W = BLOCK / 64;
+  __shared__ uint32_t ctr[W];       // one interval-barrier counter per interval
+  __shared__ uint32_t item_sh[W][2];
+  const uint32_t wave = uniform(threadIdx.x >> 6);
+  const uint32_t iw = T.iw;
+  const uint32_t k = wave / iw, wv = wave - k * iw;
+  const uint32_t pullers = gridDim.x * (W / iw);
+  if (threadIdx.x < W) ctr[threadIdx.x] = 0u;
+  if (wv == 0u && lane_id() == 0u)
+    item_sh[k][0] = __hip_atomic_fetch_add(T.queue, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();  // the only whole-workgroup barrier: counters zero, first items visible
+  PartBarrier bar(&ctr[k], iw);
+  uint32_t* lds = T.hist_words ? hf_batch_hist_lds + k * T.hist_words : nullptr;
+  for (uint32_t it = 0;; it ^= 1u) {
+    const uint32_t item = uniform(item_sh[k][it]);
+    if (item >= T.total_items) {
+      // the last of the launch's past-the-end pulls resets the queue
+      if (wv == 0u && lane_id() == 0u && item == T.total_items + pullers - 1u)
+        __hip_atomic_store(T.queue, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      break;
+    }
+    // the next item is pulled now; its latency hides behind this item's work
+    if (wv == 0u && lane_id() == 0u)
+      item_sh[k][it ^ 1u] = __hip_atomic_fetch_add(T.queue, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t t = uniform(T.item_task[item]);
+    const Part p{threadIdx.x - 64u * iw * k, 64u * iw, wv, iw, uniform(T.item_vwg[item]), uniform(T.nvwg[t])};
+    DevTask dt;
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(&T.tasks[t]);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(&dt);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(DevTask) / 4); ++i) dst[i] = uniform(src[i]);
+    run_body<HASH>((int)uniform((uint32_t)T.kinds[t]), dt, p, bar, lds);
+    bar.sync();  // every wavefront of the interval is done with this item and read the next one
+  }
+}
+
 // ------------------------------------------------------------------ host side
 struct Batch {
   int device = 0, block = 256, ntask = 0, ngroup = 0;
@@ -135,6 +197,8 @@ struct Batch {
   void* dmem = nullptr;     // tables + queue
   void* scratch = nullptr;  // per-task scratch regions
   BatchTables tab{};
+  BatchDynTables dyn{};
+  int interval_waves = 0;  // 0: one interval per group member; else worker intervals of this many waves
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipStream_t cap = nullptr;
@@ -150,6 +214,18 @@ static const void* batch_kernel(int block, bool hash) {
                           : reinterpret_cast<const void*>(&k_batch<512, false, 5>);
     case 1024: return hash ? reinterpret_cast<const void*>(&k_batch<1024, true, 4>)
                            : reinterpret_cast<const void*>(&k_batch<1024, false, 5>);
+  }
+  return nullptr;
+}
+
+static const void* batch_dyn_kernel(int block, bool hash) {
+  switch (block) {
+    case 256: return hash ? reinterpret_cast<const void*>(&k_batch_dyn<256, true, 4>)
+                          : reinterpret_cast<const void*>(&k_batch_dyn<256, false, 5>);
+    case 512: return hash ? reinterpret_cast<const void*>(&k_batch_dyn<512, true, 4>)
+                          : reinterpret_cast<const void*>(&k_batch_dyn<512, false, 5>);
+    case 1024: return hash ? reinterpret_cast<const void*>(&k_batch_dyn<1024, true, 4>)
+                           : reinterpret_cast<const void*>(&k_batch_dyn<1024, false, 5>);
   }
   return nullptr;
 }
@@ -225,22 +301,35 @@ static int batch_free(Batch* B) {
 }
 
 static int batch_launch(Batch* B, hipStream_t st) {
-  void* args[] = {&B->tab};
-  hipError_t e =
-      hipLaunchKernel(batch_kernel(B->block, B->hash), dim3(B->grid), dim3(B->block), args, B->lds_bytes, st);
+  hipError_t e;
+  if (B->interval_waves) {
+    void* args[] = {&B->dyn};
+    e = hipLaunchKernel(batch_dyn_kernel(B->block, B->hash), dim3(B->grid), dim3(B->block), args, B->lds_bytes, st);
+  } else {
+    void* args[] = {&B->tab};
+    e = hipLaunchKernel(batch_kernel(B->block, B->hash), dim3(B->grid), dim3(B->block), args, B->lds_bytes, st);
+  }
   return e == hipSuccess ? HF_OK : record_hip(e);
 }
 
+// Host-side checks and tables of a batch under `sc`; nothing is launched.
 static int batch_create(const hf_task* tasks, int ntask, const int32_t* group_of_task,
-                        const int32_t* waves_of_task, int block, Batch** out) {
+                        const int32_t* waves_of_task, const hf_batch_schedule& sc, Batch** out) {
   if (!tasks || ntask < 1 || !group_of_task || !out) return HF_EINVAL;
+  const int block = sc.block;
   if (check_block(block) != HF_OK) return HF_EINVAL;
   const int W = block / 64;
+  const int iw = sc.interval_waves;
+  if (iw < 0 || (iw > 0 && (iw > W || W % iw != 0))) return HF_EINVAL;
+  if (sc.item_kb < 0 || sc.item_kb > (1 << 20)) return HF_EINVAL;
+  if (iw > 0 && waves_of_task) return HF_EINVAL;  // worker intervals have one size for every task
   int rc;
   // groups: consecutive runs of equal ids, ids nondecreasing, 1..4 members
   std::vector<int32_t> first{0};
+  bool any_hist = false;
   for (int i = 0; i < ntask; ++i) {
     if ((rc = validate_task(&tasks[i])) != HF_OK) return rc;
+    any_hist = any_hist || tasks[i].kind == HF_LDS_HIST;
     if (i > 0 && group_of_task[i] != group_of_task[i - 1]) {
       if (group_of_task[i] < group_of_task[i - 1]) return HF_EINVAL;
       first.push_back(i);
@@ -252,11 +341,13 @@ static int batch_create(const hf_task* tasks, int ntask, const int32_t* group_of
   int max_hist = 0;
   for (int g = 0; g < ngroup; ++g) {
     const int n = first[g + 1] - first[g];
+    if (n > kMaxMembers) return HF_EINVAL;
+    if (iw > 0) continue;
     int nh = 0;
     for (int i = first[g]; i < first[g + 1]; ++i)
       if (tasks[i].kind == HF_LDS_HIST) slot[i] = nh++;
     max_hist = std::max(max_hist, nh);
-    if (n > kMaxMembers || n > W) return HF_EINVAL;
+    if (n > W) return HF_EINVAL;
     if (waves_of_task) {
       int sum = 0;
       for (int i = first[g]; i < first[g + 1]; ++i) {
@@ -275,6 +366,10 @@ static int batch_create(const hf_task* tasks, int ntask, const int32_t* group_of
       w1[i] = w;
     }
   }
+  const size_t hist_words = LdsHist::lds_words(block);
+  const size_t lds_bytes = iw > 0 ? (any_hist ? (size_t)(W / iw) * hist_words * 4u : 0u)
+                                  : (size_t)max_hist * hist_words * 4u;
+  if (lds_bytes > 160u * 1024u - 1024u) return HF_EUNSUPPORTED;  // with the static LDS, past the CU's 160 KiB
   DeviceState* s = device_state(&rc);
   if (!s) return rc;
   Batch* B = new Batch();
@@ -282,6 +377,7 @@ static int batch_create(const hf_task* tasks, int ntask, const int32_t* group_of
   B->block = block;
   B->ntask = ntask;
   B->ngroup = ngroup;
+  B->interval_waves = iw;
   B->tasks.assign(tasks, tasks + ntask);
   // scratch: one 256-byte aligned region per task that needs it
   std::vector<size_t> soff(ntask, 0);
@@ -305,79 +401,131 @@ static int batch_create(const hf_task* tasks, int ntask, const int32_t* group_of
       return record_hip(e);
     }
   }
-  // device task arguments and virtual workgroups per group
-  const char* ikb = std::getenv("HF_BATCH_ITEM_KB");
-  const double item_bytes = 1024.0 * std::max(1, ikb ? std::atoi(ikb) : 256);
+  // device task arguments; virtual workgroups: enough for every member's
+  // units, but items of about item_bytes of traffic, so that the per-item
+  // synchronisation stays cheap
+  const double item_bytes = 1024.0 * (sc.item_kb > 0 ? sc.item_kb : 256);
   std::vector<DevTask> dts(ntask);
   std::vector<int32_t> kinds(ntask);
-  std::vector<uint32_t> nwg(ngroup), istart(ngroup + 1, 0);
-  for (int g = 0; g < ngroup; ++g) {
-    int64_t need = 1;
-    double bytes = 0;
-    for (int i = first[g]; i < first[g + 1]; ++i) {
-      void* scr = tasks[i].scratch ? tasks[i].scratch
-                                   : (scratch_bytes(&tasks[i]) > 0 ? (char*)B->scratch + soff[i] : nullptr);
-      if ((rc = prepare(&tasks[i], scr, &dts[i])) != HF_OK) {
-        batch_free(B);
-        return rc;
-      }
-      kinds[i] = tasks[i].kind;
-      B->hash = B->hash || is_hash_kind(tasks[i].kind);
-      need = std::max(need, useful_wgs(&tasks[i], dts[i], waves[i]));
-      bytes += est_cost_us(&tasks[i]) * 5.0e6;
+  for (int i = 0; i < ntask; ++i) {
+    void* scr = tasks[i].scratch ? tasks[i].scratch
+                                 : (scratch_bytes(&tasks[i]) > 0 ? (char*)B->scratch + soff[i] : nullptr);
+    if ((rc = prepare(&tasks[i], scr, &dts[i])) != HF_OK) {
+      batch_free(B);
+      return rc;
     }
-    // enough virtual workgroups for every member's units, but items of about
-    // item_bytes of traffic, so that the per-item barriers stay cheap
-    const int64_t by_bytes = std::max<int64_t>(1, (int64_t)(bytes / item_bytes));
-    nwg[g] = (uint32_t)std::max<int64_t>(1, std::min<int64_t>(need, by_bytes));
-    istart[g + 1] = istart[g] + nwg[g];
+    kinds[i] = tasks[i].kind;
+    B->hash = B->hash || is_hash_kind(tasks[i].kind);
   }
-  B->total_items = istart[ngroup];
-  // one device allocation for every table
   auto al = [](size_t v) { return (v + 255) & ~size_t(255); };
-  const size_t o_tasks = 0, o_kinds = al(o_tasks + sizeof(DevTask) * ntask),
-               o_w0 = al(o_kinds + 4 * ntask), o_w1 = al(o_w0 + 4 * ntask), o_slot = al(o_w1 + 4 * ntask),
-               o_first = al(o_slot + 4 * ntask),
-               o_istart = al(o_first + 4 * (ngroup + 1)), o_nwg = al(o_istart + 4 * (ngroup + 1)),
-               o_queue = al(o_nwg + 4 * ngroup), total = al(o_queue + 4);
-  if ((e = hipMalloc(&B->dmem, total)) != hipSuccess) {
-    batch_free(B);
-    record_hip(e);
-    return HF_ENOMEM;
+  std::vector<char> host;
+  char* d = nullptr;
+  if (iw == 0) {
+    std::vector<uint32_t> nwg(ngroup), istart(ngroup + 1, 0);
+    for (int g = 0; g < ngroup; ++g) {
+      int64_t need = 1;
+      double bytes = 0;
+      for (int i = first[g]; i < first[g + 1]; ++i) {
+        need = std::max(need, useful_wgs(&tasks[i], dts[i], waves[i]));
+        bytes += est_cost_us(&tasks[i]) * 5.0e6;
+      }
+      const int64_t by_bytes = std::max<int64_t>(1, (int64_t)(bytes / item_bytes));
+      nwg[g] = (uint32_t)std::max<int64_t>(1, std::min<int64_t>(need, by_bytes));
+      istart[g + 1] = istart[g] + nwg[g];
+    }
+    B->total_items = istart[ngroup];
+    const size_t o_tasks = 0, o_kinds = al(o_tasks + sizeof(DevTask) * ntask),
+                 o_w0 = al(o_kinds + 4 * ntask), o_w1 = al(o_w0 + 4 * ntask), o_slot = al(o_w1 + 4 * ntask),
+                 o_first = al(o_slot + 4 * ntask), o_istart = al(o_first + 4 * (ngroup + 1)),
+                 o_nwg = al(o_istart + 4 * (ngroup + 1)), o_queue = al(o_nwg + 4 * ngroup), total = al(o_queue + 4);
+    host.assign(total, 0);
+    std::memcpy(host.data() + o_tasks, dts.data(), sizeof(DevTask) * ntask);
+    std::memcpy(host.data() + o_kinds, kinds.data(), 4 * ntask);
+    std::memcpy(host.data() + o_w0, w0.data(), 4 * ntask);
+    std::memcpy(host.data() + o_w1, w1.data(), 4 * ntask);
+    std::memcpy(host.data() + o_slot, slot.data(), 4 * ntask);
+    std::memcpy(host.data() + o_first, first.data(), 4 * (ngroup + 1));
+    std::memcpy(host.data() + o_istart, istart.data(), 4 * (ngroup + 1));
+    std::memcpy(host.data() + o_nwg, nwg.data(), 4 * ngroup);
+    if ((e = hipMalloc(&B->dmem, total)) != hipSuccess) {
+      batch_free(B);
+      record_hip(e);
+      return HF_ENOMEM;
+    }
+    d = static_cast<char*>(B->dmem);
+    B->tab.tasks = reinterpret_cast<const DevTask*>(d + o_tasks);
+    B->tab.kinds = reinterpret_cast<const int32_t*>(d + o_kinds);
+    B->tab.wave0 = reinterpret_cast<const int32_t*>(d + o_w0);
+    B->tab.wave1 = reinterpret_cast<const int32_t*>(d + o_w1);
+    B->tab.lds_slot = reinterpret_cast<const int32_t*>(d + o_slot);
+    B->tab.grp_first = reinterpret_cast<const int32_t*>(d + o_first);
+    B->tab.item_start = reinterpret_cast<const uint32_t*>(d + o_istart);
+    B->tab.grp_nwg = reinterpret_cast<const uint32_t*>(d + o_nwg);
+    B->tab.queue = reinterpret_cast<uint32_t*>(d + o_queue);
+    B->tab.ngroup = (uint32_t)ngroup;
+    B->tab.total_items = B->total_items;
+  } else {
+    // per-task virtual workgroups, then the queue: the members of each group
+    // interleaved item by item
+    std::vector<uint32_t> nvwg(ntask), itask, ivwg;
+    for (int i = 0; i < ntask; ++i) {
+      const int64_t by_bytes = std::max<int64_t>(1, (int64_t)(est_cost_us(&tasks[i]) * 5.0e6 / item_bytes));
+      nvwg[i] = (uint32_t)std::max<int64_t>(1, std::min<int64_t>(useful_wgs(&tasks[i], dts[i], iw), by_bytes));
+    }
+    for (int g = 0; g < ngroup; ++g) {
+      uint32_t most = 0;
+      for (int i = first[g]; i < first[g + 1]; ++i) most = std::max(most, nvwg[i]);
+      for (uint32_t b = 0; b < most; ++b)
+        for (int i = first[g]; i < first[g + 1]; ++i)
+          if (b < nvwg[i]) {
+            itask.push_back((uint32_t)i);
+            ivwg.push_back(b);
+          }
+    }
+    B->total_items = (uint32_t)itask.size();
+    const size_t o_tasks = 0, o_kinds = al(o_tasks + sizeof(DevTask) * ntask), o_nvwg = al(o_kinds + 4 * ntask),
+                 o_it = al(o_nvwg + 4 * ntask), o_iv = al(o_it + 4 * (size_t)B->total_items),
+                 o_queue = al(o_iv + 4 * (size_t)B->total_items), total = al(o_queue + 4);
+    host.assign(total, 0);
+    std::memcpy(host.data() + o_tasks, dts.data(), sizeof(DevTask) * ntask);
+    std::memcpy(host.data() + o_kinds, kinds.data(), 4 * ntask);
+    std::memcpy(host.data() + o_nvwg, nvwg.data(), 4 * ntask);
+    std::memcpy(host.data() + o_it, itask.data(), 4 * itask.size());
+    std::memcpy(host.data() + o_iv, ivwg.data(), 4 * ivwg.size());
+    if ((e = hipMalloc(&B->dmem, total)) != hipSuccess) {
+      batch_free(B);
+      record_hip(e);
+      return HF_ENOMEM;
+    }
+    d = static_cast<char*>(B->dmem);
+    B->dyn.tasks = reinterpret_cast<const DevTask*>(d + o_tasks);
+    B->dyn.kinds = reinterpret_cast<const int32_t*>(d + o_kinds);
+    B->dyn.nvwg = reinterpret_cast<const uint32_t*>(d + o_nvwg);
+    B->dyn.item_task = reinterpret_cast<const uint32_t*>(d + o_it);
+    B->dyn.item_vwg = reinterpret_cast<const uint32_t*>(d + o_iv);
+    B->dyn.queue = reinterpret_cast<uint32_t*>(d + o_queue);
+    B->dyn.total_items = B->total_items;
+    B->dyn.iw = (uint32_t)iw;
+    B->dyn.hist_words = any_hist ? (uint32_t)hist_words : 0u;
   }
-  std::vector<char> host(total, 0);
-  std::memcpy(host.data() + o_tasks, dts.data(), sizeof(DevTask) * ntask);
-  std::memcpy(host.data() + o_kinds, kinds.data(), 4 * ntask);
-  std::memcpy(host.data() + o_w0, w0.data(), 4 * ntask);
-  std::memcpy(host.data() + o_w1, w1.data(), 4 * ntask);
-  std::memcpy(host.data() + o_slot, slot.data(), 4 * ntask);
-  std::memcpy(host.data() + o_first, first.data(), 4 * (ngroup + 1));
-  std::memcpy(host.data() + o_istart, istart.data(), 4 * (ngroup + 1));
-  std::memcpy(host.data() + o_nwg, nwg.data(), 4 * ngroup);
-  if ((e = hipMemcpy(B->dmem, host.data(), total, hipMemcpyHostToDevice)) != hipSuccess) {
+  if ((e = hipMemcpy(B->dmem, host.data(), host.size(), hipMemcpyHostToDevice)) != hipSuccess) {
     batch_free(B);
     return record_hip(e);
   }
-  char* d = static_cast<char*>(B->dmem);
-  B->tab.tasks = reinterpret_cast<const DevTask*>(d + o_tasks);
-  B->tab.kinds = reinterpret_cast<const int32_t*>(d + o_kinds);
-  B->tab.wave0 = reinterpret_cast<const int32_t*>(d + o_w0);
-  B->tab.wave1 = reinterpret_cast<const int32_t*>(d + o_w1);
-  B->tab.lds_slot = reinterpret_cast<const int32_t*>(d + o_slot);
-  B->tab.grp_first = reinterpret_cast<const int32_t*>(d + o_first);
-  B->tab.item_start = reinterpret_cast<const uint32_t*>(d + o_istart);
-  B->tab.grp_nwg = reinterpret_cast<const uint32_t*>(d + o_nwg);
-  B->tab.queue = reinterpret_cast<uint32_t*>(d + o_queue);
-  B->tab.ngroup = (uint32_t)ngroup;
-  B->tab.total_items = B->total_items;
-  B->lds_bytes = (size_t)max_hist * LdsHist::lds_words(block) * 4u;
+  B->lds_bytes = lds_bytes;
+  const void* fn = iw > 0 ? batch_dyn_kernel(block, B->hash) : batch_kernel(block, B->hash);
   int occ = 0;
-  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, batch_kernel(block, B->hash), block, B->lds_bytes)) !=
-      hipSuccess) {
+  if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, block, B->lds_bytes)) != hipSuccess) {
     batch_free(B);
     return record_hip(e);
   }
-  B->grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)std::max(occ, 1) * s->num_cus, B->total_items));
+  if (occ < 1) {
+    batch_free(B);
+    return HF_EUNSUPPORTED;
+  }
+  const int64_t per_wg = iw > 0 ? W / iw : 1;  // workers per workgroup
+  const int64_t want = ((int64_t)B->total_items + per_wg - 1) / per_wg;
+  B->grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)occ * s->num_cus, want));
   *out = B;
   return HF_OK;
 }
@@ -435,14 +583,37 @@ using namespace hf;
 
 extern "C" {
 
-int hf_batch_create(const hf_task* tasks, int ntask, const int32_t* group_of_task,
-                    const int32_t* waves_of_task, int block, void** batch_out) {
-  if (!batch_out) return HF_EINVAL;
+int hf_batch_create_sched(const hf_task* tasks, int ntask, const int32_t* group_of_task,
+                          const int32_t* waves_of_task, const hf_batch_schedule* sched, void** batch_out) {
+  if (!batch_out || !sched) return HF_EINVAL;
   *batch_out = nullptr;
+  if (sched->split_policy < 0 || sched->split_policy > 1) return HF_EINVAL;
+  std::vector<int32_t> even;
+  if (!waves_of_task && sched->interval_waves == 0 && sched->split_policy == 1 && tasks && group_of_task &&
+      ntask > 0 && check_block(sched->block) == HF_OK) {
+    // the even split: every member of a group gets W / n wavefronts (the
+    // first W % n one more)
+    const int W = sched->block / 64;
+    even.assign(ntask, 1);
+    for (int i = 0; i < ntask;) {
+      int j = i;
+      while (j < ntask && group_of_task[j] == group_of_task[i]) ++j;
+      const int n = j - i;
+      for (int k = 0; k < n; ++k) even[i + k] = std::max(1, W / n + (k < W % n ? 1 : 0));
+      i = j;
+    }
+    waves_of_task = even.data();
+  }
   Batch* B = nullptr;
-  int rc = batch_create(tasks, ntask, group_of_task, waves_of_task, block, &B);
+  int rc = batch_create(tasks, ntask, group_of_task, waves_of_task, *sched, &B);
   if (rc == HF_OK) *batch_out = B;
   return rc;
+}
+
+int hf_batch_create(const hf_task* tasks, int ntask, const int32_t* group_of_task,
+                    const int32_t* waves_of_task, int block, void** batch_out) {
+  const hf_batch_schedule sc{block, 0, 0, 0};
+  return hf_batch_create_sched(tasks, ntask, group_of_task, waves_of_task, &sc, batch_out);
 }
 
 int hf_batch_run(void* batch, int use_graph, void* stream, float* ms_out) {
@@ -478,16 +649,71 @@ int hf_run_batch(const hf_task* tasks, int ntask, const int32_t* group_of_task,
   return rc;
 }
 
-// The batch schedule tuner: profiles the batch under two split policies
-// (proportional to the estimated cost, and even) at workgroup sizes 256 and
-// 512, and returns the fastest schedule's per-task waves and block.
+// Median time (ms) of `reps` timed launches of the batch under `sc` (after
+// one untimed launch); HF_EUNSUPPORTED / HF_EINVAL from creation pass through.
+static int profile_schedule(const hf_task* tasks, int ntask, const int32_t* group_of_task,
+                            const hf_batch_schedule& sc, int reps, hipStream_t st, float* med) {
+  void* b = nullptr;
+  int rc = hf_batch_create_sched(tasks, ntask, group_of_task, nullptr, &sc, &b);
+  if (rc != HF_OK) return rc;
+  std::vector<float> ts;
+  for (int r = 0; r <= reps && rc == HF_OK; ++r) {
+    float ms = 0.f;
+    rc = hf_batch_run(b, 0, st, &ms);
+    if (r > 0) ts.push_back(ms);
+  }
+  hf_batch_destroy(b);
+  if (rc != HF_OK) return rc;
+  std::sort(ts.begin(), ts.end());
+  *med = ts[ts.size() / 2];
+  return HF_OK;
+}
+
+// The schedule tuner: every static schedule (workgroup size 256, 512 or 1024;
+// wavefronts split in proportion to the estimated cost or evenly; items of
+// 128, 256 or 512 KiB) and every worker-interval schedule (workgroup size x
+// interval of 1, 2 or 4 wavefronts x items of 64, 128, 256 or 512 KiB) that
+// the batch admits, each profiled as the median of `reps` launches; writes the
+// fastest.
+int hf_batch_tune_sched(const hf_task* tasks, int ntask, const int32_t* group_of_task, int reps, void* stream,
+                        hf_batch_schedule* best_out, float* ms_out, int32_t* n_profiled) {
+  if (!tasks || ntask < 1 || !group_of_task || !best_out || reps < 1) return HF_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  std::vector<hf_batch_schedule> cands;
+  for (int block : {256, 512, 1024}) {
+    for (int pol = 0; pol < 2; ++pol)
+      for (int kb : {128, 256, 512}) cands.push_back({block, 0, kb, pol});
+    for (int iw : {1, 2, 4})
+      for (int kb : {64, 128, 256, 512}) cands.push_back({block, iw, kb, 0});
+  }
+  float best = 1e30f;
+  int nprof = 0;
+  for (const hf_batch_schedule& sc : cands) {
+    float med = 0.f;
+    const int rc = profile_schedule(tasks, ntask, group_of_task, sc, reps, st, &med);
+    if (rc == HF_EINVAL || rc == HF_EUNSUPPORTED) continue;  // this batch does not admit the schedule
+    if (rc != HF_OK) return rc;
+    ++nprof;
+    if (med < best) {
+      best = med;
+      *best_out = sc;
+    }
+  }
+  if (best >= 1e30f) return HF_EINVAL;
+  if (ms_out) *ms_out = best;
+  if (n_profiled) *n_profiled = nprof;
+  return HF_OK;
+}
+
+// The static-schedule tuner of the earlier interface: both split policies at
+// workgroup sizes 256, 512 and 1024 (items of 256 KiB); writes the fastest
+// schedule's per-task waves and block.
 int hf_batch_tune(const hf_task* tasks, int ntask, const int32_t* group_of_task, int reps, void* stream,
                   int32_t* waves_out, int32_t* block_out, float* ms_out) {
   if (!tasks || ntask < 1 || !group_of_task || !waves_out || !block_out || reps < 1) return HF_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
   float best = 1e30f;
-  const int blocks[] = {256, 512};
-  for (int block : blocks) {
+  for (int block : {256, 512, 1024}) {
     const int W = block / 64;
     for (int policy = 0; policy < 2; ++policy) {
       std::vector<int32_t> waves(ntask);
@@ -507,21 +733,11 @@ int hf_batch_tune(const hf_task* tasks, int ntask, const int32_t* group_of_task,
         i = j;
       }
       if (!ok) continue;
-      void* b = nullptr;
-      int rc = hf_batch_create(tasks, ntask, group_of_task, waves.data(), block, &b);
+      const hf_batch_schedule sc{block, 0, 256, policy};
+      float med = 0.f;
+      const int rc = profile_schedule(tasks, ntask, group_of_task, sc, reps, st, &med);
+      if (rc == HF_EINVAL || rc == HF_EUNSUPPORTED) continue;
       if (rc != HF_OK) return rc;
-      std::vector<float> ts;
-      for (int r = 0; r <= reps; ++r) {
-        float ms = 0.f;
-        if ((rc = hf_batch_run(b, 0, st, &ms)) != HF_OK) {
-          hf_batch_destroy(b);
-          return rc;
-        }
-        if (r > 0) ts.push_back(ms);
-      }
-      hf_batch_destroy(b);
-      std::sort(ts.begin(), ts.end());
-      const float med = ts[ts.size() / 2];
       if (med < best) {
         best = med;
         std::copy(waves.begin(), waves.end(), waves_out);

@@ -59,8 +59,8 @@ struct Im2colArgs {  // patches -> columns, [N][C*kh*kw][Ho*Wo]
   uint32_t vec;             // Wo % 4 == 0 and out 16-byte aligned
   FastDiv div_kk, div_row, div_kw;  // div_row: by Wo4 (vector) or Wo
   uint32_t row3;            // the 3x3 / stride 1 / pad 1 row path (see Im2col)
-  uint32_t nq;              // row path: quads of input rows per channel, ceil(H / 4)
-  uint32_t row_units;       // row path: N * C * nq
+  uint32_t nq;              // row path: quads of output rows per plane, ceil(H / 4)
+  uint32_t row_units;       // row path: N * C * 9 * nq
   FastDiv div_nq;
 };
 
@@ -541,20 +541,22 @@ struct LdsHist {
 // next to each other and find it in cache.
 //
 // Row path (3x3 kernel, stride 1, pad 1, W % 4 == 0, W <= 64, 16-byte aligned
-// input and output): with stride 1 the nine output planes of an input channel
-// are its rows shifted by -1, 0, +1 rows and columns with zero fill, so the
-// input is read once, in aligned float4, instead of once per output plane.  A
-// unit is four input rows of one channel, one row per 16-lane DPP row of the
-// wavefront (lane 16q + c holds columns 4c..4c+3 of row q; lanes with
-// c >= W/4 hold zeros).  The column shifts take the neighbouring lane's edge
-// element with a DPP row shift whose out-of-row source reads zero, which is
-// exactly the zero padding; each input row is stored to its three output rows
-// in each of the three column-shifted planes.  Each store instruction writes
-// four consecutive output rows of one plane, 64*W contiguous bytes.
+// input and output): with stride 1, output plane (i, j) of a channel is the
+// channel shifted by i - 1 rows and j - 1 columns with zero fill.  A unit is
+// four consecutive output rows of one plane, one row per 16-lane DPP row of
+// the wavefront (lane 16q + c produces columns 4c..4c+3; lanes with c >= W/4
+// hold zeros): one aligned float4 load of the source row per lane, and for a
+// column shift the neighbouring lane's edge element by a DPP row shift whose
+// out-of-row source reads zero, which is exactly the zero padding.  Each store
+// instruction writes four consecutive rows of one plane, 64*W contiguous
+// bytes, and a wavefront walks the quads of a plane in order, so its writes
+// stream through each plane front to back.  kStep units per step: their loads
+// are issued together, so the wait for them (which also waits for the previous
+// step's stores, the vector-memory counter retiring in order) comes once per
+// kStep units.
 struct Im2col {
   static constexpr uint32_t lds_words(int) { return 0; }
-
-  __device__ static __forceinline__ void zero4(float* p) { store_nt4(p, 0.f, 0.f, 0.f, 0.f); }
+  static constexpr uint32_t kStep = 4;
 
   __device__ static void run_rows(const Im2colArgs& a, const Part& p, uint32_t lane) {
     const uint32_t nw = p.nwg * p.nwaves;
@@ -565,35 +567,31 @@ struct Im2col {
     const uint32_t W = a.W, H = a.H, HW = H * W;
     const uint32_t qrow = lane >> 4, c4 = lane & 15u;
     const bool colok = c4 < W / 4u;
-    for (uint32_t u = ubeg; u < uend; ++u) {
-      const uint32_t nc = fdiv(u, a.div_nq);
-      const uint32_t ih = 4u * (u - nc * a.nq) + qrow;
-      const bool ok = colok && ih < H;
-      float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (ok) x = *reinterpret_cast<const float4*>(a.x + (size_t)nc * HW + ih * W + 4u * c4);
-      // every lane takes part in the shifts: row_shr:1 and row_shl:1, zero
-      // from outside the 16-lane row
-      const float left = dpp_f32<0x111>(x.w);
-      const float right = dpp_f32<0x101>(x.x);
-      float* planes = a.out + (size_t)nc * 9u * HW + 4u * c4;
-      if (ok) {
+    for (uint32_t u0 = ubeg; u0 < uend; u0 += kStep) {
+      float4 x[kStep];
+      uint32_t plane[kStep], oh[kStep];
 #pragma unroll
-        for (uint32_t i = 0; i < 3; ++i) {
-          const uint32_t oh = ih + 1u - i;  // wraps past H when ih + 1 < i
-          if (oh < H) {
-            float* d = planes + (size_t)(3u * i) * HW + oh * W;
-            store_nt4(d, left, x.x, x.y, x.z);
-            store_nt4(d + HW, x.x, x.y, x.z, x.w);
-            store_nt4(d + 2u * HW, x.y, x.z, x.w, right);
-          }
-        }
+      for (uint32_t k = 0; k < kStep; ++k) {
+        const uint32_t u = min(u0 + k, uend - 1u);  // a unit past the range repeats the last one
+        plane[k] = fdiv(u, a.div_nq);
+        oh[k] = 4u * (u - plane[k] * a.nq) + qrow;
+        const uint32_t nc = fdiv(plane[k], a.div_kk);
+        const uint32_t i = fdiv(plane[k] - nc * 9u, a.div_kw);
+        const uint32_t ih = oh[k] + i - 1u;  // wraps past H above the image
+        x[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (colok && oh[k] < H && ih < H)
+          x[k] = *reinterpret_cast<const float4*>(a.x + (size_t)nc * HW + ih * W + 4u * c4);
       }
-      // the rows no input row reaches: row 0 of the planes that look one row
-      // up, row H-1 of the planes that look one row down
-      if (colok && ih == 0u)
-        for (uint32_t j = 0; j < 3; ++j) zero4(planes + (size_t)j * HW);
-      if (colok && ih == H - 1u)
-        for (uint32_t j = 0; j < 3; ++j) zero4(planes + (size_t)(6u + j) * HW + (H - 1u) * W);
+#pragma unroll
+      for (uint32_t k = 0; k < kStep; ++k) {
+        const uint32_t j = plane[k] - 3u * fdiv(plane[k], a.div_kw);  // wave-uniform
+        float4 v = x[k];
+        // every lane takes part in the shifts (row_shr:1 / row_shl:1)
+        if (j == 0u) v = make_float4(dpp_f32<0x111>(x[k].w), x[k].x, x[k].y, x[k].z);
+        else if (j == 2u) v = make_float4(x[k].y, x[k].z, x[k].w, dpp_f32<0x101>(x[k].x));
+        if (colok && oh[k] < H && u0 + k < uend)
+          store_nt4(a.out + (size_t)plane[k] * HW + oh[k] * W + 4u * c4, v.x, v.y, v.z, v.w);
+      }
     }
   }
 

@@ -345,7 +345,7 @@ int prepare(const hf_task* t, void* scratch, DevTask* dt) {
       a.row3 = kh == 3 && kw == 3 && s == 1 && p == 1 && a.W % 4u == 0u && a.W <= 64u &&
                aligned(t->in, 16) && aligned(t->out0, 16);
       a.nq = (a.H + 3u) / 4u;
-      a.row_units = (uint32_t)t->n * a.C * a.nq;
+      a.row_units = (uint32_t)t->n * a.C * 9u * a.nq;
       a.div_nq = make_fastdiv(a.nq);
       return HF_OK;
     }

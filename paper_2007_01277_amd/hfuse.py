@@ -52,6 +52,14 @@ class hf_config(ctypes.Structure):
         return f"hf_config(split_waves={self.split_waves}, block={self.block}, vgpr_cap={self.vgpr_cap}, grid={self.grid})"
 
 
+class hf_batch_schedule(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("interval_waves", ctypes.c_int32), ("item_kb", ctypes.c_int32),
+                ("split_policy", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
 class hf_kernel_info(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in (
         "vgprs", "sgprs", "lds_bytes", "spill_bytes", "wg_per_cu", "waves_per_simd", "num_cus", "default_grid")]
@@ -113,6 +121,10 @@ SIGNATURES = {
     "hf_mlp_load": (_I, [ctypes.c_char_p]),
     "hf_featurize": (_I, [ctypes.POINTER(hf_pair), ctypes.POINTER(hf_config), _I, _P, _F]),
     "hf_batch_create": (_I, [ctypes.POINTER(hf_task), _I, _I32P, _I32P, _I, ctypes.POINTER(_P)]),
+    "hf_batch_create_sched": (_I, [ctypes.POINTER(hf_task), _I, _I32P, _I32P, ctypes.POINTER(hf_batch_schedule),
+                                   ctypes.POINTER(_P)]),
+    "hf_batch_tune_sched": (_I, [ctypes.POINTER(hf_task), _I, _I32P, _I, _P, ctypes.POINTER(hf_batch_schedule), _F,
+                                 _I32P]),
     "hf_batch_run": (_I, [_P, _I, _P, _F]),
     "hf_batch_info": (_I, [_P, _I32P, _I32P, _I32P]),
     "hf_batch_destroy": (_I, [_P]),
@@ -473,14 +485,19 @@ def _i32(a):
 class Batch:
     """Owns an hf_batch handle; keep the tasks' tensors alive while it is used."""
 
-    def __init__(self, tasks, groups, waves=None, block=256):
+    def __init__(self, tasks, groups, waves=None, block=256, schedule=None):
+        """`schedule` (an hf_batch_schedule) replaces `block` when given."""
         self.ntask = len(tasks)
         self._tasks = (hf_task * len(tasks))(*tasks)
         g_arr, g_ptr = _i32(groups)
         w_arr, w_ptr = _i32(waves)
         h = _P()
-        _check(lib().hf_batch_create(self._tasks, len(tasks), g_ptr, w_ptr, block, ctypes.byref(h)),
-               "hf_batch_create")
+        if schedule is None:
+            _check(lib().hf_batch_create(self._tasks, len(tasks), g_ptr, w_ptr, block, ctypes.byref(h)),
+                   "hf_batch_create")
+        else:
+            _check(lib().hf_batch_create_sched(self._tasks, len(tasks), g_ptr, w_ptr, ctypes.byref(schedule),
+                                               ctypes.byref(h)), "hf_batch_create_sched")
         self.handle = h
 
     def run(self, use_graph=False, stream=None, timed=False):
@@ -565,3 +582,15 @@ def hf_int_peak(rounds: int = 16384, grid: int = 0, stream=None):
     ops = ctypes.c_double(0.0)
     _check(lib().hf_int_peak(rounds, grid, _stream(stream), ctypes.byref(ms), ctypes.byref(ops)), "hf_int_peak")
     return ms.value, ops.value
+
+
+def hf_batch_tune_sched(tasks, groups, reps=5, stream=None):
+    """(schedule, median ms, schedules profiled) of the batch schedule search."""
+    arr = (hf_task * len(tasks))(*tasks)
+    g_arr, g_ptr = _i32(groups)
+    best = hf_batch_schedule()
+    ms = ctypes.c_float(0.0)
+    n = ctypes.c_int32(0)
+    _check(lib().hf_batch_tune_sched(arr, len(tasks), g_ptr, reps, _stream(stream), ctypes.byref(best),
+                                     ctypes.byref(ms), ctypes.byref(n)), "hf_batch_tune_sched")
+    return best, ms.value, n.value

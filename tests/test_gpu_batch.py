@@ -122,12 +122,60 @@ def test_batch_graph_replays_match_eager():
     b.close()
 
 
+def test_batch_worker_intervals_match_solo_every_schedule():
+    """Worker-interval schedules: every block x interval size x item size the
+    batch admits, eager and replayed from a graph with eager work between the
+    replays, bit-exact with the solo launches (checked against the oracle)."""
+    kinds, logs, groups = BB.draw(48, seed=15, kmin=8, kmax=15)
+    w = BB.Workload(kinds, logs, seed=15)
+    ref = solo_reference(w)
+    for k, x, o in zip(kinds, w.ins, ref):
+        check_instance(k, x, o)
+    ran = 0
+    for block in (256, 512, 1024):
+        for iw in (1, 2, 4, 8):
+            if iw > block // 64:
+                continue
+            for kb in (16, 256):
+                sc = H.hf_batch_schedule(block, iw, kb, 0)
+                try:
+                    b = H.Batch(w.tasks, groups, schedule=sc)
+                except H.HFError as e:  # a schedule whose LDS does not fit a CU
+                    assert e.status == H.HF_EUNSUPPORTED, (block, iw)
+                    continue
+                print("workers", block, iw, kb, b.info(), flush=True)
+                for use_graph in (False, True, True):
+                    w.clear()
+                    b.run(use_graph)
+                    torch.cuda.synchronize()
+                    assert BB.same(ref, w.snapshot()), (block, iw, kb, use_graph)
+                    H.hf_run_solo(w.tasks[0], 512)  # eager work between replays
+                b.close()
+                ran += 1
+    assert ran >= 14
+
+
+def test_batch_schedule_search_gives_a_valid_schedule():
+    kinds, logs, groups = BB.draw(50, seed=16, kmin=10, kmax=14)
+    w = BB.Workload(kinds, logs, seed=16)
+    ref = solo_reference(w)
+    sched, ms, nprof = H.hf_batch_tune_sched(w.tasks, groups, reps=2)
+    assert ms > 0 and nprof >= 30 and sched.block in (256, 512, 1024)
+    b = H.Batch(w.tasks, groups, schedule=sched)
+    for use_graph in (False, True):
+        w.clear()
+        b.run(use_graph)
+        torch.cuda.synchronize()
+        assert BB.same(ref, w.snapshot()), (sched.as_dict(), use_graph)
+    b.close()
+
+
 def test_batch_tune_gives_a_valid_schedule():
     kinds, logs, groups = BB.draw(50, seed=14, kmin=10, kmax=14)
     w = BB.Workload(kinds, logs, seed=14)
     ref = solo_reference(w)
     waves, block, ms = H.hf_batch_tune(w.tasks, groups, reps=3)
-    assert block in (256, 512) and ms > 0
+    assert block in (256, 512, 1024) and ms > 0
     b = H.Batch(w.tasks, groups, waves, block)
     w.clear()
     b.run(True)
@@ -158,11 +206,13 @@ def test_batch_with_hash_kinds():
     ref = solo_reference(w)
     for k, x, o, m in zip(kinds, w.ins, ref, w.meta):
         check_instance(k, x, o, m)
-    for block in (256, 1024):
-        b = H.Batch(w.tasks, groups, None, block)
+    scheds = [(256, None), (1024, None), (512, H.hf_batch_schedule(512, 2, 64, 0)),
+              (256, H.hf_batch_schedule(256, 1, 256, 0))]
+    for block, sc in scheds:
+        b = H.Batch(w.tasks, groups, None, block, schedule=sc)
         for graph in (False, True, True):
             w.clear()
             b.run(graph)
             torch.cuda.synchronize()
-            assert BB.same(ref, w.snapshot()), (block, graph)
+            assert BB.same(ref, w.snapshot()), (block, sc and sc.as_dict(), graph)
         b.close()
