@@ -556,7 +556,7 @@ struct LdsHist {
 // kStep units.
 struct Im2col {
   static constexpr uint32_t lds_words(int) { return 0; }
-  static constexpr uint32_t kStep = 4;
+  static constexpr uint32_t kStep = 8;
 
   __device__ static void run_rows(const Im2colArgs& a, const Part& p, uint32_t lane) {
     const uint32_t nw = p.nwg * p.nwaves;

@@ -112,11 +112,14 @@ __device__ __forceinline__ double wave_sum_f64(double v) {
 // q = n / d for 0 <= n < 2^31: with l = ceil(log2 d) and m = ceil(2^(31+l) / d),
 // floor(n*m / 2^(31+l)) = floor(n/d) (Granlund & Montgomery, PLDI 1994), and m
 // fits in 32 bits.  For d >= 2 the shift is >= 32, so only the high word of the
-// product is needed.  d == 1 is flagged by m == 0.
+// product is needed.  d == 1 has m = 0 and an all-ones `id` mask that adds n
+// back, so the quotient is one multiply-high, an and-or and a shift with no
+// branch (a branch per division would split the kernels' loops into blocks).
 struct FastDiv {
   uint32_t d;
   uint32_t m;
   uint32_t sh;  // 31 + l - 32
+  uint32_t id;  // 0xFFFFFFFF when d == 1, else 0
 };
 
 inline FastDiv make_fastdiv(uint32_t d) {
@@ -125,6 +128,7 @@ inline FastDiv make_fastdiv(uint32_t d) {
   if (d <= 1) {
     f.m = 0;
     f.sh = 0;
+    f.id = 0xFFFFFFFFu;
     return f;
   }
   uint32_t l = 0;
@@ -132,11 +136,12 @@ inline FastDiv make_fastdiv(uint32_t d) {
   const uint64_t num = 1ull << (31 + l);  // l <= 31, so this fits
   f.m = (uint32_t)((num + d - 1) / d);
   f.sh = 31 + l - 32;
+  f.id = 0u;
   return f;
 }
 
 __host__ __device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv& f) {
-  return f.m == 0 ? n : ((uint32_t)(((uint64_t)n * f.m) >> 32) >> f.sh);
+  return ((uint32_t)(((uint64_t)n * f.m) >> 32) | (n & f.id)) >> f.sh;
 }
 
 }  // namespace hf

@@ -238,9 +238,9 @@ def evaluate(data, folds: int = 4, per_pair: int = 14, topk: int = 3, epochs: in
              lr: float = 1e-3, seed: int = 7, ks=(1, 2, 3, 5, 8, 12), members: int = MEMBERS):
     """Regret of the learned tuner on held-out pairs.  The model (an ensemble
     of `members` networks) is trained on t_rel = log2(T_fused) - log2(t_a +
-    t_b), which removes each pair's scale; the order of its predictions within
-    a pair is what the tuner uses, profiling the k best with distinct (split,
-    block) (pick_topk)."""
+    t_b), which removes each pair's scale, centred per training pair; the
+    order of its predictions within a pair is what the tuner uses, profiling
+    the k best with distinct (split, block) (pick_topk)."""
     X, y, pair, cand = data["X"], data["y"], data["pair"], data["cand"]
     yrel = y - X[:, SUM_SOLO]
     keys = data["cands"]
@@ -260,8 +260,14 @@ def evaluate(data, folds: int = 4, per_pair: int = 14, topk: int = 3, epochs: in
             idx = [i for i in tr if pair[i] == p]
             keep += g.choice(idx, size=min(per_pair, len(idx)), replace=False).tolist()
         keep = np.array(sorted(keep))
+        # targets centred per training pair: only the order within a pair is
+        # used, and a pair's level is what the features predict worst
+        yt = yrel[keep].copy()
+        for p in set(pair[keep].tolist()):
+            m = pair[keep] == p
+            yt[m] -= yt[m].mean()
         H.hf_mlp_init(X.shape[1], 1000 * (seed + f), members=members)
-        train_loss.append(H.hf_mlp_train(X[keep], yrel[keep], epochs=epochs, lr=lr))
+        train_loss.append(H.hf_mlp_train(X[keep], yt, epochs=epochs, lr=lr))
         for p in sorted(test):
             idx = np.where(pair == p)[0]
             ty = y[idx]
@@ -287,7 +293,9 @@ def evaluate(data, folds: int = 4, per_pair: int = 14, topk: int = 3, epochs: in
                    # profiling cost of the learned tuner (featurisation + its top k) over the exhaustive one
                    "cost_fraction": float((featurisation_ms(X[idx[0]]) + (TUNE_REPS + 1) * np.sum(2.0 ** ty[top]))
                                           / ((TUNE_REPS + 1) * np.sum(2.0 ** ty))),
-                   "pred_rmse_log2": float(np.sqrt(np.mean((pred - yrel[idx]) ** 2)))}
+                   # within-pair error: both sides centred (the targets were)
+                   "pred_rmse_log2": float(np.sqrt(np.mean(((pred - pred.mean()) - (yrel[idx] - yrel[idx].mean()))
+                                                           ** 2)))}
             res["per_pair"].append(rec)
     pp = res["per_pair"]
     for k in ("regret_mlp", "regret_naive", "regret_r0", "regret_random", "rank_corr", "pred_rmse_log2",
