@@ -415,7 +415,7 @@ int hf_batch_create_sched(const hf_task* tasks, int ntask, const int32_t* group_
                           const int32_t* waves_of_task, const hf_batch_schedule* sched, void** batch_out);
 /* Schedule search over both kinds of schedule: static (blocks 256/512/1024 x
  * split policy x items of 128/256/512 KiB) and worker intervals (blocks x
- * intervals of 1/2/4 wavefronts x items of 64/128/256/512 KiB), every
+ * intervals of 1/2/4/8 wavefronts x items of 64/128/256/512 KiB), every
  * schedule the batch admits profiled as the median of `reps` launches.
  * Writes the fastest schedule, its median time and the number profiled. */
 int hf_batch_tune_sched(const hf_task* tasks, int ntask, const int32_t* group_of_task, int reps, void* stream,

@@ -20,6 +20,7 @@ Modes timed (median of `reps` runs, events on the launch stream):
   batch_graph    the same launch replayed from a captured HIP graph
 
     python -m paper_2007_01277_amd.batch_bench --count 1000 --out batch.json
+    python -m paper_2007_01277_amd.batch_bench --schedule 512,4,64,0   (a fixed schedule)
 """
 from __future__ import annotations
 
@@ -131,7 +132,7 @@ def same(a, b):
     return all(all(bool((p == q).all()) for p, q in zip(x, y)) for x, y in zip(a, b))
 
 
-def run_modes(w: Workload, groups, reps: int = 10, block=None, waves=None, log=sys.stderr):
+def run_modes(w: Workload, groups, reps: int = 10, block=None, waves=None, log=sys.stderr, schedule=None):
     import torch
     st = torch.cuda.current_stream()
     side = [torch.cuda.Stream() for _ in range(3)]
@@ -183,7 +184,10 @@ def run_modes(w: Workload, groups, reps: int = 10, block=None, waves=None, log=s
     res["graph_solo_ms"] = timed(g.replay)
     res["graph_solo_equal"] = same(ref, w.snapshot())
     # the tuned schedule of the persistent fused kernel
-    if block is None:
+    if schedule is not None:
+        b = H.Batch(w.tasks, groups, schedule=schedule)
+        res["schedule"] = {**schedule.as_dict(), **b.info()}
+    elif block is None:
         t0 = time.time()
         sched, tms, nprof = H.hf_batch_tune_sched(w.tasks, groups, reps=5)
         res["tune_s"] = round(time.time() - t0, 3)
@@ -213,6 +217,8 @@ def main(argv=None):
     ap.add_argument("--kmax", type=int, default=18)
     ap.add_argument("--reps", type=int, default=10)
     ap.add_argument("--out", default="")
+    ap.add_argument("--schedule", default="",
+                    help="block,interval_waves,item_kb,split_policy: a fixed schedule instead of the search")
     a = ap.parse_args(argv)
     import torch
     torch.cuda.set_device(0)
@@ -220,7 +226,8 @@ def main(argv=None):
     kinds, logs, groups = draw(a.count, kmin=a.kmin, kmax=a.kmax)
     w = Workload(kinds, logs)
     H.hf_warmup(300)
-    res, _ = run_modes(w, groups, reps=a.reps)
+    sched = H.hf_batch_schedule(*[int(v) for v in a.schedule.split(",")]) if a.schedule else None
+    res, _ = run_modes(w, groups, reps=a.reps, schedule=sched)
     res.update({"count": a.count, "groups": len(set(groups)), "elements": w.elements(), "bytes": w.bytes()})
     print(json.dumps(res), flush=True)
     if a.out:

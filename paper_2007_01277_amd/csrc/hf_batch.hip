@@ -672,7 +672,7 @@ static int profile_schedule(const hf_task* tasks, int ntask, const int32_t* grou
 // The schedule tuner: every static schedule (workgroup size 256, 512 or 1024;
 // wavefronts split in proportion to the estimated cost or evenly; items of
 // 128, 256 or 512 KiB) and every worker-interval schedule (workgroup size x
-// interval of 1, 2 or 4 wavefronts x items of 64, 128, 256 or 512 KiB) that
+// interval of 1, 2, 4 or 8 wavefronts x items of 64, 128, 256 or 512 KiB) that
 // the batch admits, each profiled as the median of `reps` launches; writes the
 // fastest.
 int hf_batch_tune_sched(const hf_task* tasks, int ntask, const int32_t* group_of_task, int reps, void* stream,
@@ -683,8 +683,9 @@ int hf_batch_tune_sched(const hf_task* tasks, int ntask, const int32_t* group_of
   for (int block : {256, 512, 1024}) {
     for (int pol = 0; pol < 2; ++pol)
       for (int kb : {128, 256, 512}) cands.push_back({block, 0, kb, pol});
-    for (int iw : {1, 2, 4})
-      for (int kb : {64, 128, 256, 512}) cands.push_back({block, iw, kb, 0});
+    for (int iw : {1, 2, 4, 8})
+      if (iw <= block / 64)
+        for (int kb : {64, 128, 256, 512}) cands.push_back({block, iw, kb, 0});
   }
   float best = 1e30f;
   int nprof = 0;

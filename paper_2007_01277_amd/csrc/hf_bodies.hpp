@@ -59,9 +59,10 @@ struct Im2colArgs {  // patches -> columns, [N][C*kh*kw][Ho*Wo]
   uint32_t vec;             // Wo % 4 == 0 and out 16-byte aligned
   FastDiv div_kk, div_row, div_kw;  // div_row: by Wo4 (vector) or Wo
   uint32_t row3;            // the 3x3 / stride 1 / pad 1 row path (see Im2col)
-  uint32_t nq;              // row path: quads of output rows per plane, ceil(H / 4)
+  uint32_t nch;             // row path: chunks of 64 columns per row, ceil(W / 64)
+  uint32_t nq;              // row path: units per plane, ceil(H * nch / 4)
   uint32_t row_units;       // row path: N * C * 9 * nq
-  FastDiv div_nq;
+  FastDiv div_nq, div_nch;
 };
 
 struct UpArgs {  // bilinear upsampling by integer factor s, half-pixel centres
@@ -75,6 +76,11 @@ struct UpArgs {  // bilinear upsampling by integer factor s, half-pixel centres
   uint32_t lanes_per_unit;  // rows_per_unit * Wo4 (vector) or * Wo
   uint32_t vec;             // Wo % 4 == 0 and out 16-byte aligned
   FastDiv div_ho, div_row;  // div_row: by Wo4 (vector) or Wo
+  uint32_t row2;            // the scale-2 row path (see Upsample)
+  uint32_t nch;             // row path: chunks of 32 input columns per row, ceil(W / 32)
+  uint32_t nq;              // row path: units per plane, ceil(Ho * nch / 4)
+  uint32_t row_units;       // row path: N * C * nq
+  FastDiv div_nq, div_nch;
 };
 
 struct PoolArgs {  // max pooling with the winner's flat index
@@ -86,9 +92,10 @@ struct PoolArgs {  // max pooling with the winner's flat index
   uint32_t units;  // ceil(total / Maxpool::kUnit)
   FastDiv div_plane, div_wo;  // by Ho*Wo and by Wo
   uint32_t row3;       // the 3x3 / stride 2 / pad 1 row path (see Maxpool)
-  uint32_t nq;         // row path: quads of output rows per plane, ceil(Ho / 4)
+  uint32_t nch;        // row path: chunks of 128 input columns per row, ceil(W / 128)
+  uint32_t nq;         // row path: units per plane, ceil(Ho * nch / 4)
   uint32_t row_units;  // row path: planes * nq
-  FastDiv div_nq;
+  FastDiv div_nq, div_nch;
 };
 
 struct ShaArgs {  // SHA-256d and BLAKE2b over header || nonce
@@ -540,23 +547,24 @@ struct LdsHist {
 // fastest-varying unit index, so the kh*kw planes that read one input plane run
 // next to each other and find it in cache.
 //
-// Row path (3x3 kernel, stride 1, pad 1, W % 4 == 0, W <= 64, 16-byte aligned
-// input and output): with stride 1, output plane (i, j) of a channel is the
-// channel shifted by i - 1 rows and j - 1 columns with zero fill.  A unit is
-// four consecutive output rows of one plane, one row per 16-lane DPP row of
-// the wavefront (lane 16q + c produces columns 4c..4c+3; lanes with c >= W/4
-// hold zeros): one aligned float4 load of the source row per lane, and for a
-// column shift the neighbouring lane's edge element by a DPP row shift whose
-// out-of-row source reads zero, which is exactly the zero padding.  Each store
-// instruction writes four consecutive rows of one plane, 64*W contiguous
-// bytes, and a wavefront walks the quads of a plane in order, so its writes
-// stream through each plane front to back.  kStep units per step: their loads
-// are issued together, so the wait for them (which also waits for the previous
-// step's stores, the vector-memory counter retiring in order) comes once per
-// kStep units.
+// Row path (3x3 kernel, stride 1, pad 1, W % 4 == 0, 16-byte aligned input and
+// output): with stride 1, output plane (i, j) of a channel is the channel
+// shifted by i - 1 rows and j - 1 columns with zero fill.  Each output row is
+// cut into chunks of 64 columns; a unit is four consecutive chunks of one plane
+// (four rows when W <= 64), one chunk per 16-lane DPP row of the wavefront:
+// lane 16q + c produces columns 4c..4c+3 of its chunk from one aligned float4
+// of the source row, and a column shift takes the neighbouring lane's edge
+// element with a DPP row shift.  The first lane of a chunk takes the element
+// left of it, and the last lane the element right of it, with one extra dword
+// load (zero at the image's edge).  All accesses go through buffer resources
+// over one plane: rows and columns outside the image load zero, which is
+// exactly the zero padding, and lanes past the plane's end store nothing, so
+// the loop has no branch around a memory access.  Each store instruction
+// writes four chunks of one plane, front to back.  kStep units per step: their
+// loads are issued together, so the wait for them comes once per kStep units.
 struct Im2col {
   static constexpr uint32_t lds_words(int) { return 0; }
-  static constexpr uint32_t kStep = 8;
+  static constexpr uint32_t kStep = 7;
 
   __device__ static void run_rows(const Im2colArgs& a, const Part& p, uint32_t lane) {
     const uint32_t nw = p.nwg * p.nwaves;
@@ -564,33 +572,48 @@ struct Im2col {
     const uint32_t q = a.row_units / nw, r = a.row_units - q * nw;
     const uint32_t ubeg = gw * q + min(gw, r);
     const uint32_t uend = ubeg + q + (gw < r ? 1u : 0u);
-    const uint32_t W = a.W, H = a.H, HW = H * W;
+    const uint32_t W = a.W, H = a.H, HW = H * W, pbytes = 4u * HW;
     const uint32_t qrow = lane >> 4, c4 = lane & 15u;
-    const bool colok = c4 < W / 4u;
+    // The output position of unit u in this lane (shared by both phases; the
+    // store phase recomputes it rather than keep kStep more registers live).
+    auto where = [&](uint32_t u, uint32_t& plane, uint32_t& oh, uint32_t& col) {
+      plane = fdiv(u, a.div_nq);
+      const uint32_t cid = 4u * (u - plane * a.nq) + qrow;  // chunk of this DPP row
+      oh = fdiv(cid, a.div_nch);
+      col = 64u * (cid - oh * a.nch) + 4u * c4;
+    };
     for (uint32_t u0 = ubeg; u0 < uend; u0 += kStep) {
       float4 x[kStep];
-      uint32_t plane[kStep], oh[kStep];
+      float edge[kStep];
 #pragma unroll
       for (uint32_t k = 0; k < kStep; ++k) {
-        const uint32_t u = min(u0 + k, uend - 1u);  // a unit past the range repeats the last one
-        plane[k] = fdiv(u, a.div_nq);
-        oh[k] = 4u * (u - plane[k] * a.nq) + qrow;
-        const uint32_t nc = fdiv(plane[k], a.div_kk);
-        const uint32_t i = fdiv(plane[k] - nc * 9u, a.div_kw);
-        const uint32_t ih = oh[k] + i - 1u;  // wraps past H above the image
-        x[k] = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (colok && oh[k] < H && ih < H)
-          x[k] = *reinterpret_cast<const float4*>(a.x + (size_t)nc * HW + ih * W + 4u * c4);
+        uint32_t plane, oh, col;
+        where(min(u0 + k, uend - 1u), plane, oh, col);  // a unit past the range repeats the last one
+        const uint32_t nc = fdiv(plane, a.div_kk);
+        const uint32_t i = fdiv(plane - nc * 9u, a.div_kw);
+        const uint32_t ih = oh + i - 1u;  // wraps past H above the image
+        const bool rowok = oh < H && col < W && ih < H;
+        const __amdgpu_buffer_rsrc_t src = buffer_rsrc(a.x + (size_t)nc * HW, pbytes);
+        x[k] = buffer_load4(src, rowok ? 4u * (ih * W + col) : kOutOfRange);
+        uint32_t eo = kOutOfRange;
+        if (c4 == 0u && col > 0u) eo = 4u * (ih * W + col - 1u);
+        if (c4 == 15u && col + 4u < W) eo = 4u * (ih * W + col + 4u);
+        edge[k] = buffer_load1(src, rowok ? eo : kOutOfRange);
       }
 #pragma unroll
       for (uint32_t k = 0; k < kStep; ++k) {
-        const uint32_t j = plane[k] - 3u * fdiv(plane[k], a.div_kw);  // wave-uniform
-        float4 v = x[k];
+        uint32_t plane, oh, col;
+        where(min(u0 + k, uend - 1u), plane, oh, col);
+        const uint32_t at = (oh < H && col < W && u0 + k < uend) ? 4u * (oh * W + col) : kOutOfRange;
+        const uint32_t j = plane - 3u * fdiv(plane, a.div_kw);  // wave-uniform
         // every lane takes part in the shifts (row_shr:1 / row_shl:1)
-        if (j == 0u) v = make_float4(dpp_f32<0x111>(x[k].w), x[k].x, x[k].y, x[k].z);
-        else if (j == 2u) v = make_float4(x[k].y, x[k].z, x[k].w, dpp_f32<0x101>(x[k].x));
-        if (colok && oh[k] < H && u0 + k < uend)
-          store_nt4(a.out + (size_t)plane[k] * HW + oh[k] * W + 4u * c4, v.x, v.y, v.z, v.w);
+        const float sl = dpp_f32<0x111>(x[k].w), sr = dpp_f32<0x101>(x[k].x);
+        const float lft = c4 == 0u ? edge[k] : sl;
+        const float rgt = c4 == 15u ? edge[k] : sr;
+        float4 v = x[k];
+        if (j == 0u) v = make_float4(lft, x[k].x, x[k].y, x[k].z);
+        else if (j == 2u) v = make_float4(x[k].y, x[k].z, x[k].w, rgt);
+        buffer_store4_nt(buffer_rsrc(a.out + (size_t)plane * HW, pbytes), at, v.x, v.y, v.z, v.w);
       }
     }
   }
@@ -661,6 +684,80 @@ struct Upsample {
 
   __device__ static __forceinline__ float lerp(float a, float b, float l) { return a + l * (b - a); }
 
+  // Row path (scale 2, W even, 8-byte aligned input, 16-byte aligned output).
+  // Each output row is cut into chunks that read 32 input columns and write 64
+  // output columns; a unit is four consecutive chunks of one plane (four output
+  // rows when W <= 32), one chunk per 16-lane DPP row.  Lane 16q + c reads input
+  // columns 2c, 2c+1 of the output row's two source rows (one float2 each) and
+  // writes output columns 4c..4c+3 (one float4), so every store instruction
+  // covers whole contiguous lines.  Column 2c-1 comes from the lane before and
+  // column 2c+2 from the lane after by DPP row shifts, from one extra dword load
+  // at a chunk's first and last lane, and from the lane itself at the image's
+  // edges (the coordinate clamp).  The four outputs are the general scale-2
+  // path's expressions of the same inputs, so both paths give the same bits.
+  // Buffer accesses keep the loop free of branches around memory instructions;
+  // kStep units per step.
+  static constexpr uint32_t kStep = 4;
+
+  __device__ static void run_rows(const UpArgs& a, const Part& p, uint32_t lane) {
+    const uint32_t nw = p.nwg * p.nwaves;
+    const uint32_t gw = p.wg * p.nwaves + p.wave;
+    const uint32_t q = a.row_units / nw, r = a.row_units - q * nw;
+    const uint32_t ubeg = gw * q + min(gw, r);
+    const uint32_t uend = ubeg + q + (gw < r ? 1u : 0u);
+    const uint32_t W = a.W, HW = a.H * a.W, OHW = a.Ho * a.Wo;
+    const uint32_t qrow = lane >> 4, c4 = lane & 15u;
+    auto where = [&](uint32_t u, uint32_t& plane, uint32_t& oy, uint32_t& col) {
+      plane = fdiv(u, a.div_nq);
+      const uint32_t cid = 4u * (u - plane * a.nq) + qrow;  // chunk of this DPP row
+      oy = fdiv(cid, a.div_nch);
+      col = 32u * (cid - oy * a.nch) + 2u * c4;  // first input column of this lane
+    };
+    for (uint32_t u0 = ubeg; u0 < uend; u0 += kStep) {
+      float2 x0[kStep], x1[kStep];
+      float e0[kStep], e1[kStep];
+#pragma unroll
+      for (uint32_t k = 0; k < kStep; ++k) {
+        uint32_t plane, oy, col;
+        where(min(u0 + k, uend - 1u), plane, oy, col);  // a unit past the range repeats the last one
+        uint32_t y0, y1;
+        float ly;
+        coord(min(oy, a.Ho - 1u), a.inv_s, a.H, y0, y1, ly);
+        const bool ok = oy < a.Ho && col < W;
+        const __amdgpu_buffer_rsrc_t src = buffer_rsrc(a.x + (size_t)plane * HW, 4u * HW);
+        uint32_t eo = kOutOfRange;  // the column left or right of the lane's two, if another lane's
+        if (c4 == 0u && col > 0u) eo = col - 1u;
+        if (c4 == 15u && col + 2u < W) eo = col + 2u;
+        x0[k] = buffer_load2(src, ok ? 4u * (y0 * W + col) : kOutOfRange);
+        x1[k] = buffer_load2(src, ok ? 4u * (y1 * W + col) : kOutOfRange);
+        e0[k] = buffer_load1(src, ok && eo != kOutOfRange ? 4u * (y0 * W + eo) : kOutOfRange);
+        e1[k] = buffer_load1(src, ok && eo != kOutOfRange ? 4u * (y1 * W + eo) : kOutOfRange);
+      }
+#pragma unroll
+      for (uint32_t k = 0; k < kStep; ++k) {
+        uint32_t plane, oy, col;
+        where(min(u0 + k, uend - 1u), plane, oy, col);
+        uint32_t y0, y1;
+        float ly;
+        coord(min(oy, a.Ho - 1u), a.inv_s, a.H, y0, y1, ly);
+        // every lane takes part in the shifts (row_shr:1 / row_shl:1)
+        const float l0 = dpp_f32<0x111>(x0[k].y), r0 = dpp_f32<0x101>(x0[k].x);
+        const float l1 = dpp_f32<0x111>(x1[k].y), r1 = dpp_f32<0x101>(x1[k].x);
+        const bool first = col == 0u, last = col + 2u >= W;
+        const float p0 = first ? x0[k].x : (c4 == 0u ? e0[k] : l0), p1 = x0[k].x, p2 = x0[k].y;
+        const float p3 = last ? x0[k].y : (c4 == 15u ? e0[k] : r0);
+        const float q0 = first ? x1[k].x : (c4 == 0u ? e1[k] : l1), q1 = x1[k].x, q2 = x1[k].y;
+        const float q3 = last ? x1[k].y : (c4 == 15u ? e1[k] : r1);
+        const uint32_t at = (oy < a.Ho && col < W && u0 + k < uend) ? 4u * (oy * a.Wo + 2u * col) : kOutOfRange;
+        buffer_store4_nt(buffer_rsrc(a.out + (size_t)plane * OHW, 4u * OHW), at,
+                         lerp(lerp(p0, p1, 0.75f), lerp(q0, q1, 0.75f), ly),
+                         lerp(lerp(p1, p2, 0.25f), lerp(q1, q2, 0.25f), ly),
+                         lerp(lerp(p1, p2, 0.75f), lerp(q1, q2, 0.75f), ly),
+                         lerp(lerp(p2, p3, 0.25f), lerp(q2, q3, 0.25f), ly));
+      }
+    }
+  }
+
   __device__ static __forceinline__ float sample(const float* r0, const float* r1, float ly, uint32_t W,
                                                  uint32_t ox, float inv_s) {
     uint32_t x0, x1;
@@ -675,6 +772,10 @@ struct Upsample {
   __device__ static void run(const DevTask& dt, const Part& p, Bar&, uint32_t*) {
     const UpArgs& a = dt.up;
     const uint32_t lane = lane_id();
+    if (a.row2) {
+      run_rows(a, p, lane);
+      return;
+    }
     const uint32_t nw = p.nwg * p.nwaves;
     const uint32_t HW = a.H * a.W;
     const bool x2 = a.vec && a.Wo == 2u * a.W;  // scale 2 with float4 stores
@@ -730,16 +831,21 @@ struct Upsample {
 // later element wins only if greater or NaN) the winner and its index are
 // exactly those of the unclamped scan.  All loads are therefore unconditional.
 //
-// Row path (3x3 window, stride 2, pad 1, W % 8 == 0, W <= 128, 16-byte
-// aligned buffers): a unit is four output rows of one plane, one per 16-lane
-// DPP row of the wavefront.  Lane 16q + c computes outputs 4c..4c+3 of its
-// row, whose windows span input columns 8c-1 .. 8c+7 of three input rows:
-// columns 8c..8c+7 are two aligned float4 per row, and column 8c-1 is the left
-// neighbour lane's last element, taken with a DPP row shift (at c = 0 the
-// column clamps to 0, as in the general path).  Rows clamp the same way.
-// Each window is scanned in the general path's order, and values and indices
-// are stored as float4 / int4, four output rows per store instruction.
+// Row path (3x3 window, stride 2, pad 1, W % 8 == 0, 16-byte aligned
+// buffers): each output row is cut into chunks that read 128 input columns
+// and write 64 outputs; a unit is four consecutive chunks of one plane (four
+// output rows when W <= 128), one per 16-lane DPP row of the wavefront.  Lane
+// 16q + c computes outputs 4c..4c+3 of its chunk, whose windows span input
+// columns 8c-1 .. 8c+7 (chunk-relative) of three input rows: columns 8c..8c+7
+// are two aligned float4 per row, and column 8c-1 is the left neighbour lane's
+// last element, taken with a DPP row shift, or, at a chunk's first lane, one
+// extra dword load (at the image's first column the column clamps to 0, as in
+// the general path).  Rows clamp the same way.  Each window is scanned in the
+// general path's order, and values and indices are stored as float4 / int4
+// through buffer resources (lanes past the plane's end store nothing), four
+// chunks per store instruction.
 struct Maxpool {
+  static constexpr int kSoloWaves = 8;  // 45 VGPRs, but 106 SGPRs would allow only 7
   static constexpr uint32_t kPer = 2;
   static constexpr uint32_t kUnit = 64 * kPer;
   static constexpr uint32_t lds_words(int) { return 0; }
@@ -757,50 +863,56 @@ struct Maxpool {
     const uint32_t q = a.row_units / nw, r = a.row_units - q * nw;
     const uint32_t ubeg = gw * q + min(gw, r);
     const uint32_t uend = ubeg + q + (gw < r ? 1u : 0u);
-    const uint32_t W = a.W, Wo4 = a.Wo / 4u;
-    const uint32_t qrow = lane >> 4, c = lane & 15u;
-    const uint32_t cc = min(c, Wo4 - 1u);  // lanes past the row load in bounds and store nothing
+    const uint32_t W = a.W, HW = a.H * a.W, OHW = a.Ho * a.Wo;
+    const uint32_t qrow = lane >> 4, c4 = lane & 15u;
     for (uint32_t u = ubeg; u < uend; ++u) {
       const uint32_t plane = fdiv(u, a.div_nq);
-      const uint32_t oh = 4u * (u - plane * a.nq) + qrow;
-      const bool ok = c < Wo4 && oh < a.Ho;
+      const uint32_t cid = 4u * (u - plane * a.nq) + qrow;  // chunk of this DPP row
+      const uint32_t oh = fdiv(cid, a.div_nch);
+      const uint32_t col = 128u * (cid - oh * a.nch) + 8u * c4;  // first input column of this lane
+      const bool ok = oh < a.Ho && col < W;
       const uint32_t ohc = min(oh, a.Ho - 1u);
-      const float* img = a.x + (size_t)plane * a.H * W;
+      const __amdgpu_buffer_rsrc_t src = buffer_rsrc(a.x + (size_t)plane * HW, 4u * HW);
+      float4 A[3], B[3];
+      float E[3];
+#pragma unroll
+      for (uint32_t i = 0; i < 3; ++i) {
+        const uint32_t h = (uint32_t)clampi((int32_t)(2u * ohc + i) - 1, (int32_t)a.H - 1);
+        A[i] = buffer_load4(src, ok ? 4u * (h * W + col) : kOutOfRange);
+        B[i] = buffer_load4(src, ok ? 4u * (h * W + col + 4u) : kOutOfRange);
+        // column col - 1 of the first lane of a chunk that is not the image's first
+        E[i] = buffer_load1(src, ok && c4 == 0u && col > 0u ? 4u * (h * W + col - 1u) : kOutOfRange);
+      }
       float best[4];
       int32_t at[4];
 #pragma unroll
       for (uint32_t i = 0; i < 3; ++i) {
         const int32_t h = clampi((int32_t)(2u * ohc + i) - 1, (int32_t)a.H - 1);
-        const float* rowp = img + (size_t)h * W + 8u * cc;
-        const float4 A = *reinterpret_cast<const float4*>(rowp);
-        const float4 B = *reinterpret_cast<const float4*>(rowp + 4);
-        const float lft = dpp_f32<0x111>(B.w);  // column 8c - 1 from lane c - 1 of this row
-        const int32_t e0 = h * (int32_t)W + 8 * (int32_t)cc;
-        const float L = cc == 0u ? A.x : lft;
-        const int32_t eL = cc == 0u ? e0 : e0 - 1;
+        const float lft = dpp_f32<0x111>(B[i].w);  // column col - 1 from the lane before
+        const int32_t e0 = h * (int32_t)W + (int32_t)col;
+        // at the image's first column the window's clamped column is column 0
+        const float L = col == 0u ? A[i].x : (c4 == 0u ? E[i] : lft);
+        const int32_t eL = col == 0u ? e0 : e0 - 1;
         const bool f = i == 0;
         take(L, eL, f, best[0], at[0]);
-        take(A.x, e0, false, best[0], at[0]);
-        take(A.y, e0 + 1, false, best[0], at[0]);
-        take(A.y, e0 + 1, f, best[1], at[1]);
-        take(A.z, e0 + 2, false, best[1], at[1]);
-        take(A.w, e0 + 3, false, best[1], at[1]);
-        take(A.w, e0 + 3, f, best[2], at[2]);
-        take(B.x, e0 + 4, false, best[2], at[2]);
-        take(B.y, e0 + 5, false, best[2], at[2]);
-        take(B.y, e0 + 5, f, best[3], at[3]);
-        take(B.z, e0 + 6, false, best[3], at[3]);
-        take(B.w, e0 + 7, false, best[3], at[3]);
+        take(A[i].x, e0, false, best[0], at[0]);
+        take(A[i].y, e0 + 1, false, best[0], at[0]);
+        take(A[i].y, e0 + 1, f, best[1], at[1]);
+        take(A[i].z, e0 + 2, false, best[1], at[1]);
+        take(A[i].w, e0 + 3, false, best[1], at[1]);
+        take(A[i].w, e0 + 3, f, best[2], at[2]);
+        take(B[i].x, e0 + 4, false, best[2], at[2]);
+        take(B[i].y, e0 + 5, false, best[2], at[2]);
+        take(B[i].y, e0 + 5, f, best[3], at[3]);
+        take(B[i].z, e0 + 6, false, best[3], at[3]);
+        take(B[i].w, e0 + 7, false, best[3], at[3]);
       }
-      if (ok) {
-        const size_t o = (size_t)plane * a.Ho * a.Wo + (size_t)oh * a.Wo + 4u * c;
-        store_nt4(a.out + o, best[0], best[1], best[2], best[3]);
-        if (a.idx) {
-          typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
-          const i32x4 v = {at[0], at[1], at[2], at[3]};
-          __builtin_nontemporal_store(v, reinterpret_cast<i32x4*>(a.idx + o));
-        }
-      }
+      const uint32_t o = ok ? 4u * (oh * a.Wo + col / 2u) : kOutOfRange;
+      buffer_store4_nt(buffer_rsrc(a.out + (size_t)plane * OHW, 4u * OHW), o, best[0], best[1], best[2], best[3]);
+      if (a.idx)
+        buffer_store4_nt(buffer_rsrc(a.idx + (size_t)plane * OHW, 4u * OHW), o, __builtin_bit_cast(float, at[0]),
+                         __builtin_bit_cast(float, at[1]), __builtin_bit_cast(float, at[2]),
+                         __builtin_bit_cast(float, at[3]));
     }
   }
 

@@ -46,6 +46,42 @@ __device__ __forceinline__ void store_nt4(float* p, float a, float b, float c, f
   __builtin_nontemporal_store(v, reinterpret_cast<f32x4*>(p));
 }
 
+// ----------------------------------------------------------------- buffer accesses
+// A raw buffer resource (stride 0) over `bytes` bytes from `base`: every access
+// through it is range-checked by the hardware, a load whose offset is out of
+// range returns zero and a store whose offset is out of range is dropped.
+// Zero padding and ragged edges then need no branch around a memory
+// instruction: an invalid lane gets the offset kOutOfRange.  With no branches,
+// the compiler counts outstanding loads exactly and waits only for the one a
+// use needs (a load under a branch makes it wait for every older access).
+// `bytes` must be below 2^31 and the resource must lie inside the allocation.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+constexpr uint32_t kOutOfRange = 0x80000000u;
+constexpr int kAuxNT = 2;  // cache policy bits of a non-temporal access
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+// (whole vectors are bit-cast: a bit cast of one element of a vector value
+// reads element 0 in this compiler)
+__device__ __forceinline__ float4 buffer_load4(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  const f32x4 v = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0));
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ float2 buffer_load2(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  typedef float f32x2 __attribute__((ext_vector_type(2)));
+  const f32x2 v = __builtin_bit_cast(f32x2, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+  return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ float buffer_load1(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+}
+__device__ __forceinline__ void buffer_store4_nt(__amdgpu_buffer_rsrc_t r, uint32_t off, float a, float b,
+                                                 float c, float d) {
+  const f32x4 v = {a, b, c, d};
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, (int)off, 0, kAuxNT);
+}
+
 // ----------------------------------------------------------------- barriers
 struct WGBarrier {
   __device__ __forceinline__ void sync() { __syncthreads(); }

@@ -12,6 +12,7 @@
 // WPE > 0 asks the compiler for at least WPE resident wavefronts per SIMD, which
 // bounds the VGPRs per lane to 512/WPE: the register bound of Sec. III-B.
 #pragma once
+#include <type_traits>
 #include "hf_bodies.hpp"
 
 namespace hf {
@@ -82,10 +83,22 @@ __global__ void __launch_bounds__(BLOCK) vfused(DevTask ta, DevTask tb) {
   K2::run(tb, p, bar, smem);
 }
 
+// Waves per SIMD the solo kernel of body K asks the compiler to fit (its
+// kSoloWaves, else no request): a body whose scalar registers would otherwise
+// cost it a wavefront per SIMD sets 8.
+template <class K, class = void>
+struct SoloWaves {
+  static constexpr int v = 1;
+};
+template <class K>
+struct SoloWaves<K, std::void_t<decltype(K::kSoloWaves)>> {
+  static constexpr int v = K::kSoloWaves;
+};
+
 // The original kernel: the whole workgroup is one interval and its barrier is
 // the native s_barrier.
 template <class K, int BLOCK>
-__global__ void __launch_bounds__(BLOCK) solo(DevTask t) {
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(SoloWaves<K>::v))) solo(DevTask t) {
   __shared__ uint32_t smem[max1(K::lds_words(BLOCK))];
   const Part p{threadIdx.x, (uint32_t)BLOCK, uniform(threadIdx.x >> 6), (uint32_t)(BLOCK / 64),
                blockIdx.x, gridDim.x};

@@ -342,11 +342,14 @@ int prepare(const hf_task* t, void* scratch, DevTask* dt) {
       a.div_kk = make_fastdiv(a.KK);
       a.div_row = make_fastdiv(rowlen);
       a.div_kw = make_fastdiv(kw);
-      a.row3 = kh == 3 && kw == 3 && s == 1 && p == 1 && a.W % 4u == 0u && a.W <= 64u &&
-               aligned(t->in, 16) && aligned(t->out0, 16);
-      a.nq = (a.H + 3u) / 4u;
+      // the row path addresses one plane through a buffer resource of < 2^31 bytes
+      a.row3 = kh == 3 && kw == 3 && s == 1 && p == 1 && a.W % 4u == 0u &&
+               (uint64_t)a.H * a.W * 4u < (1ull << 31) && aligned(t->in, 16) && aligned(t->out0, 16);
+      a.nch = (a.W + 63u) / 64u;
+      a.nq = (uint32_t)(((uint64_t)a.H * a.nch + 3u) / 4u);
       a.row_units = (uint32_t)t->n * a.C * 9u * a.nq;
       a.div_nq = make_fastdiv(a.nq);
+      a.div_nch = make_fastdiv(a.nch);
       return HF_OK;
     }
     case HF_UPSAMPLE: {
@@ -367,6 +370,15 @@ int prepare(const hf_task* t, void* scratch, DevTask* dt) {
       a.lanes_per_unit = a.rows_per_unit * rowlen;
       a.div_ho = make_fastdiv(a.Ho);
       a.div_row = make_fastdiv(rowlen);
+      // the row path addresses one input and one output plane through buffer
+      // resources of < 2^31 bytes
+      a.row2 = s == 2u && a.W % 2u == 0u && (uint64_t)a.Ho * a.Wo * 4u < (1ull << 31) && aligned(t->in, 8) &&
+               aligned(t->out0, 16);
+      a.nch = (a.W + 31u) / 32u;
+      a.nq = (uint32_t)(((uint64_t)a.Ho * a.nch + 3u) / 4u);
+      a.row_units = (uint32_t)t->n * (uint32_t)t->c * a.nq;
+      a.div_nq = make_fastdiv(a.nq);
+      a.div_nch = make_fastdiv(a.nch);
       return HF_OK;
     }
     case HF_MAXPOOL: {
@@ -386,11 +398,15 @@ int prepare(const hf_task* t, void* scratch, DevTask* dt) {
       a.units = (a.total + Maxpool::kUnit - 1u) / Maxpool::kUnit;
       a.div_plane = make_fastdiv(a.Ho * a.Wo);
       a.div_wo = make_fastdiv(a.Wo);
-      a.row3 = a.kh == 3u && a.kw == 3u && a.s == 2u && a.p == 1u && a.W % 8u == 0u && a.W <= 128u &&
-               aligned(t->in, 16) && aligned(t->out0, 16) && aligned(t->out1, 16);
-      a.nq = (a.Ho + 3u) / 4u;
+      // the row path addresses one plane through buffer resources of < 2^31 bytes
+      a.row3 = a.kh == 3u && a.kw == 3u && a.s == 2u && a.p == 1u && a.W % 8u == 0u &&
+               (uint64_t)a.H * a.W * 4u < (1ull << 31) && aligned(t->in, 16) && aligned(t->out0, 16) &&
+               aligned(t->out1, 16);
+      a.nch = (a.W + 127u) / 128u;
+      a.nq = (uint32_t)(((uint64_t)a.Ho * a.nch + 3u) / 4u);
       a.row_units = (uint32_t)t->n * (uint32_t)t->c * a.nq;
       a.div_nq = make_fastdiv(a.nq);
+      a.div_nch = make_fastdiv(a.nch);
       return HF_OK;
     }
     case HF_SHA256D:
@@ -426,7 +442,7 @@ int64_t useful_wgs(const hf_task* t, const DevTask& d, int waves) {
     case HF_INT_MIX: units = cdiv(d.mix.n4 ? d.mix.n4 : d.mix.n, 64 * waves); break;
     case HF_LDS_HIST: units = cdiv(std::max<uint32_t>(d.hist.n16, 1), 64 * waves); break;
     case HF_IM2COL: units = cdiv(d.im2col.row3 ? d.im2col.row_units : d.im2col.units, waves); break;
-    case HF_UPSAMPLE: units = cdiv(d.up.units, waves); break;
+    case HF_UPSAMPLE: units = cdiv(d.up.row2 ? d.up.row_units : d.up.units, waves); break;
     case HF_MAXPOOL: units = cdiv(d.pool.row3 ? d.pool.row_units : d.pool.units, waves); break;
     case HF_SHA256D:
     case HF_BLAKE2B: units = cdiv(d.sha.n, 64 * waves); break;

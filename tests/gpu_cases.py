@@ -259,20 +259,33 @@ def small_cases(kind, seed=0):
     if kind == H.HF_LDS_HIST:
         return [hist_case(1 << 20, seed), hist_case(100_003, seed, offset=3), hist_case(50_000, seed, zipf=False)]
     if kind == H.HF_IM2COL:
-        # the first and the last three take the 3x3/s1/p1 row path (rows in
-        # 16-lane groups: a width of 64 fills a group, 4 is one column of
-        # float4, heights not a multiple of 4 leave a partial quad)
+        # the first and the last six take the 3x3/s1/p1 row path (64-column
+        # chunks in 16-lane groups: a width of 64 fills a chunk, 4 is one
+        # float4 column, 68 leaves a chunk of one column, 200 and 1024 span
+        # several chunks per row, heights not a multiple of 4 leave a partial
+        # unit)
         return [im2col_case((2, 8, 14, 16), seed=seed), im2col_case((2, 3, 9, 11), (3, 3), 2, 1, seed),
                 im2col_case((1, 4, 6, 7), (2, 3), 1, 0, seed), im2col_case((1, 3, 5, 64), seed=seed),
-                im2col_case((2, 2, 2, 4), seed=seed), im2col_case((1, 5, 1, 60), seed=seed)]
+                im2col_case((2, 2, 2, 4), seed=seed), im2col_case((1, 5, 1, 60), seed=seed),
+                im2col_case((1, 2, 5, 68), seed=seed), im2col_case((2, 2, 3, 200), seed=seed),
+                im2col_case((1, 3, 6, 1024), seed=seed)]
     if kind == H.HF_UPSAMPLE:
-        return [up_case((2, 8, 16, 16), 2, seed), up_case((1, 3, 5, 7), 3, seed), up_case((2, 2, 9, 33), 2, seed)]
+        # the first and the last four take the scale-2 row path (32 input
+        # columns per 16-lane group: 34 leaves a chunk of one lane, 68, 200 and
+        # 1024 span several chunks per row); 33 is odd
+        return [up_case((2, 8, 16, 16), 2, seed), up_case((1, 3, 5, 7), 3, seed), up_case((2, 2, 9, 33), 2, seed),
+                up_case((1, 2, 4, 34), 2, seed), up_case((1, 2, 5, 68), 2, seed), up_case((1, 3, 3, 200), 2, seed),
+                up_case((1, 2, 2, 1024), 2, seed)]
     if kind == H.HF_MAXPOOL:
-        # the last three take the 3x3/s2/p1 row path (a width of 128 fills a
-        # 16-lane row group, 8 is one float4 of outputs, odd heights clamp)
+        # the last six take the 3x3/s2/p1 row path (128 input columns per
+        # 16-lane group: 128 fills one, 8 is one float4 of outputs, 136 leaves a
+        # chunk of one lane, 256 and 1024 span several chunks per row, odd
+        # heights clamp)
         return [pool_case((2, 8, 24, 20), seed=seed), pool_case((1, 3, 9, 11), (2, 2), 2, 0, seed, offset=1),
                 pool_case((2, 2, 7, 13), (3, 2), 1, 1, seed, with_idx=False), pool_case((2, 3, 10, 16), seed=seed),
-                pool_case((1, 2, 7, 128), seed=seed), pool_case((1, 4, 16, 8), seed=seed, with_idx=False)]
+                pool_case((1, 2, 7, 128), seed=seed), pool_case((1, 4, 16, 8), seed=seed, with_idx=False),
+                pool_case((1, 3, 6, 136), seed=seed), pool_case((1, 2, 7, 256), seed=seed),
+                pool_case((2, 2, 5, 1024), seed=seed, with_idx=False)]
     if kind in (H.HF_SHA256D, H.HF_BLAKE2B, H.HF_ETHASH):
         # several waves of work, a ragged tail, and a nonce range that wraps past 2^32
         return [hash_case(kind, 1000, seed), hash_case(kind, 333, seed + 1, nonce0=0xFFFFFF00, rows=37),
