@@ -60,8 +60,8 @@ struct Im2colArgs {  // patches -> columns, [N][C*kh*kw][Ho*Wo]
   FastDiv div_kk, div_row, div_kw;  // div_row: by Wo4 (vector) or Wo
   uint32_t row3;            // the 3x3 / stride 1 / pad 1 row path (see Im2col)
   uint32_t nch;             // row path: chunks of 64 columns per row, ceil(W / 64)
-  uint32_t nq;              // row path: units per plane, ceil(H * nch / 4)
-  uint32_t row_units;       // row path: N * C * 9 * nq
+  uint32_t nq;              // row path: units per channel, ceil(H * nch / 4)
+  uint32_t row_units;       // row path: N * C * nq
   FastDiv div_nq, div_nch;
 };
 
@@ -549,22 +549,26 @@ struct LdsHist {
 //
 // Row path (3x3 kernel, stride 1, pad 1, W % 4 == 0, 16-byte aligned input and
 // output): with stride 1, output plane (i, j) of a channel is the channel
-// shifted by i - 1 rows and j - 1 columns with zero fill.  Each output row is
-// cut into chunks of 64 columns; a unit is four consecutive chunks of one plane
-// (four rows when W <= 64), one chunk per 16-lane DPP row of the wavefront:
-// lane 16q + c produces columns 4c..4c+3 of its chunk from one aligned float4
-// of the source row, and a column shift takes the neighbouring lane's edge
-// element with a DPP row shift.  The first lane of a chunk takes the element
-// left of it, and the last lane the element right of it, with one extra dword
-// load (zero at the image's edge).  All accesses go through buffer resources
-// over one plane: rows and columns outside the image load zero, which is
-// exactly the zero padding, and lanes past the plane's end store nothing, so
-// the loop has no branch around a memory access.  Each store instruction
-// writes four chunks of one plane, front to back.  kStep units per step: their
-// loads are issued together, so the wait for them comes once per kStep units.
+// shifted by i - 1 rows and j - 1 columns with zero fill, so one output row of
+// all nine planes is made from three input rows.  Each row is cut into chunks
+// of 64 columns; a unit is four consecutive chunks of one channel (four rows
+// when W <= 64), one chunk per 16-lane DPP row of the wavefront.  Lane 16q + c
+// loads columns 4c..4c+3 of input rows oh-1, oh, oh+1 (one aligned float4 each)
+// and writes columns 4c..4c+3 of row oh of all nine planes: a column shift
+// takes the neighbouring lane's edge element with a DPP row shift, and the
+// first and last lane of a chunk take the element beyond it with one extra
+// dword load per row (zero at the image's edge).  Every input element is thus
+// loaded by one unit only (plus the rows shared with the neighbouring quads,
+// which the same wavefront reads next), instead of once per plane.  All
+// accesses go through buffer resources over one plane: rows and columns
+// outside the image load zero, which is exactly the zero padding, and lanes
+// past the plane's end store nothing, so the loop has no branch around a
+// memory access.  Each store instruction writes four chunks of one plane.
+// kStep units per step: their loads are issued together, so the wait for them
+// comes once per kStep units.
 struct Im2col {
   static constexpr uint32_t lds_words(int) { return 0; }
-  static constexpr uint32_t kStep = 7;
+  static constexpr uint32_t kStep = 3;
 
   __device__ static void run_rows(const Im2colArgs& a, const Part& p, uint32_t lane) {
     const uint32_t nw = p.nwg * p.nwaves;
@@ -574,46 +578,50 @@ struct Im2col {
     const uint32_t uend = ubeg + q + (gw < r ? 1u : 0u);
     const uint32_t W = a.W, H = a.H, HW = H * W, pbytes = 4u * HW;
     const uint32_t qrow = lane >> 4, c4 = lane & 15u;
-    // The output position of unit u in this lane (shared by both phases; the
-    // store phase recomputes it rather than keep kStep more registers live).
-    auto where = [&](uint32_t u, uint32_t& plane, uint32_t& oh, uint32_t& col) {
-      plane = fdiv(u, a.div_nq);
-      const uint32_t cid = 4u * (u - plane * a.nq) + qrow;  // chunk of this DPP row
+    // The channel and output position of unit u in this lane (shared by both
+    // phases; the store phase recomputes it rather than keep registers live).
+    auto where = [&](uint32_t u, uint32_t& nc, uint32_t& oh, uint32_t& col) {
+      nc = fdiv(u, a.div_nq);
+      const uint32_t cid = 4u * (u - nc * a.nq) + qrow;  // chunk of this DPP row
       oh = fdiv(cid, a.div_nch);
       col = 64u * (cid - oh * a.nch) + 4u * c4;
     };
     for (uint32_t u0 = ubeg; u0 < uend; u0 += kStep) {
-      float4 x[kStep];
-      float edge[kStep];
+      float4 x[kStep][3];
+      float edge[kStep][3];
 #pragma unroll
       for (uint32_t k = 0; k < kStep; ++k) {
-        uint32_t plane, oh, col;
-        where(min(u0 + k, uend - 1u), plane, oh, col);  // a unit past the range repeats the last one
-        const uint32_t nc = fdiv(plane, a.div_kk);
-        const uint32_t i = fdiv(plane - nc * 9u, a.div_kw);
-        const uint32_t ih = oh + i - 1u;  // wraps past H above the image
-        const bool rowok = oh < H && col < W && ih < H;
+        uint32_t nc, oh, col;
+        where(min(u0 + k, uend - 1u), nc, oh, col);  // a unit past the range repeats the last one
         const __amdgpu_buffer_rsrc_t src = buffer_rsrc(a.x + (size_t)nc * HW, pbytes);
-        x[k] = buffer_load4(src, rowok ? 4u * (ih * W + col) : kOutOfRange);
-        uint32_t eo = kOutOfRange;
-        if (c4 == 0u && col > 0u) eo = 4u * (ih * W + col - 1u);
-        if (c4 == 15u && col + 4u < W) eo = 4u * (ih * W + col + 4u);
-        edge[k] = buffer_load1(src, rowok ? eo : kOutOfRange);
+        uint32_t ec = kOutOfRange;  // the column left or right of the lane's four, if another lane's
+        if (c4 == 0u && col > 0u) ec = col - 1u;
+        if (c4 == 15u && col + 4u < W) ec = col + 4u;
+#pragma unroll
+        for (uint32_t i = 0; i < 3u; ++i) {
+          const uint32_t ih = oh + i - 1u;  // wraps past H above the image
+          const bool rowok = oh < H && col < W && ih < H;
+          x[k][i] = buffer_load4(src, rowok ? 4u * (ih * W + col) : kOutOfRange);
+          edge[k][i] = buffer_load1(src, rowok && ec != kOutOfRange ? 4u * (ih * W + ec) : kOutOfRange);
+        }
       }
 #pragma unroll
       for (uint32_t k = 0; k < kStep; ++k) {
-        uint32_t plane, oh, col;
-        where(min(u0 + k, uend - 1u), plane, oh, col);
+        uint32_t nc, oh, col;
+        where(min(u0 + k, uend - 1u), nc, oh, col);
         const uint32_t at = (oh < H && col < W && u0 + k < uend) ? 4u * (oh * W + col) : kOutOfRange;
-        const uint32_t j = plane - 3u * fdiv(plane, a.div_kw);  // wave-uniform
-        // every lane takes part in the shifts (row_shr:1 / row_shl:1)
-        const float sl = dpp_f32<0x111>(x[k].w), sr = dpp_f32<0x101>(x[k].x);
-        const float lft = c4 == 0u ? edge[k] : sl;
-        const float rgt = c4 == 15u ? edge[k] : sr;
-        float4 v = x[k];
-        if (j == 0u) v = make_float4(lft, x[k].x, x[k].y, x[k].z);
-        else if (j == 2u) v = make_float4(x[k].y, x[k].z, x[k].w, rgt);
-        buffer_store4_nt(buffer_rsrc(a.out + (size_t)plane * HW, pbytes), at, v.x, v.y, v.z, v.w);
+#pragma unroll
+        for (uint32_t i = 0; i < 3u; ++i) {
+          const float4 v = x[k][i];
+          // every lane takes part in the shifts (row_shr:1 / row_shl:1)
+          const float sl = dpp_f32<0x111>(v.w), sr = dpp_f32<0x101>(v.x);
+          const float lft = c4 == 0u ? edge[k][i] : sl;
+          const float rgt = c4 == 15u ? edge[k][i] : sr;
+          const float* base = a.out + ((size_t)nc * 9u + 3u * i) * HW;  // plane (i, 0) of channel nc
+          buffer_store4_nt(buffer_rsrc(base, pbytes), at, lft, v.x, v.y, v.z);
+          buffer_store4_nt(buffer_rsrc(base + HW, pbytes), at, v.x, v.y, v.z, v.w);
+          buffer_store4_nt(buffer_rsrc(base + 2u * (size_t)HW, pbytes), at, v.y, v.z, v.w, rgt);
+        }
       }
     }
   }

@@ -347,7 +347,7 @@ int prepare(const hf_task* t, void* scratch, DevTask* dt) {
                (uint64_t)a.H * a.W * 4u < (1ull << 31) && aligned(t->in, 16) && aligned(t->out0, 16);
       a.nch = (a.W + 63u) / 64u;
       a.nq = (uint32_t)(((uint64_t)a.H * a.nch + 3u) / 4u);
-      a.row_units = (uint32_t)t->n * a.C * 9u * a.nq;
+      a.row_units = (uint32_t)t->n * a.C * a.nq;
       a.div_nq = make_fastdiv(a.nq);
       a.div_nch = make_fastdiv(a.nch);
       return HF_OK;
