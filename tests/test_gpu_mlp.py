@@ -138,19 +138,23 @@ def test_ensemble_trains_and_roundtrips_through_a_file():
     assert np.array_equal(H.hf_mlp_predict(Xt), pred)
 
 
-def test_learned_tuner_beats_the_untuned_choice():
-    """On pairs of the five data kernels (the learned-tuner workload): trains on
-    tuner-profiled samples of 75 pairs (14 configurations each) and ranks every
-    candidate of 25 held-out pairs: the model's top-3 choice has a lower regret
-    than the even split (the method without the network) and than 3 candidates
-    profiled at random, at 3/85 of the exhaustive search's cost."""
-    pairs = LT.draw_pairs(100, seed=5, kmin=16, kmax=22, kinds=LT.DATA_KINDS)
-    data = LT.collect(pairs, reps=5, seed=5)
-    res = LT.evaluate(data, folds=4, per_pair=14, topk=3, epochs=500)
+def test_learned_tuner_at_the_workload_shape():
+    """The learned tuner's workload as the bench runs it: 40 seeded pairs of the
+    five data kernels, every candidate profiled twice (two independent
+    measurements), the ensemble trained on 50 configurations of each training
+    pair, 4-fold cross-validation by pair, top 3 of 85 profiled.  On the second
+    measurement the tuner's choice is within 5 % of the exhaustive search's
+    choice on average; on the first (where the exhaustive best is the minimum
+    of 85 noisy values) within 9 %; and it beats the even split and 3
+    candidates profiled at random on both."""
+    pairs = LT.draw_pairs(40, seed=2, kmin=16, kmax=26, kinds=LT.DATA_KINDS)
+    data = LT.collect(pairs, reps=10, seed=2, check=True)
+    res = LT.evaluate(data, folds=4, per_pair=50, topk=3, epochs=500)
     print({k: v for k, v in res.items() if k != "per_pair"}, flush=True)
-    assert res["regret_mlp_mean"] < res["regret_naive_mean"]
-    assert res["regret_mlp_mean"] < res["regret_random_mean_at_k"][3]
-    assert res["regret_mlp_mean"] <= 0.08
+    assert res["regret_mlp_checked_mean"] <= 0.05
+    assert res["regret_mlp_mean"] <= 0.09
+    assert res["regret_mlp_mean"] < min(res["regret_naive_mean"], res["regret_random_mean"])
+    assert res["regret_mlp_checked_mean"] < min(res["regret_naive_checked_mean"], res["regret_random_checked_mean"])
 
 
 def test_hf_tune_mlp_profiles_only_topk():
