@@ -242,13 +242,20 @@ def featurisation_ms(x) -> float:
     return t
 
 
+CLIP = 0.3  # training targets above a pair's best by more than this (log2) are clipped to it
+
+
 def evaluate(data, folds: int = 4, per_pair: int = 14, topk: int = 3, epochs: int = 500,
-             lr: float = 1e-3, seed: int = 7, ks=(1, 2, 3, 5, 8, 12), members: int = MEMBERS):
+             lr: float = 1e-3, seed: int = 7, ks=(1, 2, 3, 5, 8, 12), members: int = MEMBERS,
+             clip: float = CLIP):
     """Regret of the learned tuner on held-out pairs.  The model (an ensemble
     of `members` networks) is trained on t_rel = log2(T_fused) - log2(t_a +
-    t_b), which removes each pair's scale, centred per training pair; the
-    order of its predictions within a pair is what the tuner uses, profiling
-    the k best with distinct (split, block) (pick_topk).
+    t_b), which removes each pair's scale; per training pair the targets are
+    clipped at the pair's best + `clip` (a configuration 2^0.3 = 1.23 times
+    slower than the best, or more, is "bad" and its exact slowness is noise
+    for the choice) and centred.  The order of the predictions within a pair
+    is what the tuner uses, profiling the k best with distinct (split, block)
+    (pick_topk).
 
     Regret = T(best of the k profiled) / T(exhaustive best) - 1 on the
     measurements the choices were made on.  With a second measurement of every
@@ -279,11 +286,14 @@ def evaluate(data, folds: int = 4, per_pair: int = 14, topk: int = 3, epochs: in
             idx = [i for i in tr if pair[i] == p]
             keep += g.choice(idx, size=min(per_pair, len(idx)), replace=False).tolist()
         keep = np.array(sorted(keep))
-        # targets centred per training pair: only the order within a pair is
-        # used, and a pair's level is what the features predict worst
+        # targets clipped and centred per training pair: only the order near
+        # the top within a pair is used, and a pair's level is what the
+        # features predict worst
         yt = yrel[keep].copy()
         for p in set(pair[keep].tolist()):
             m = pair[keep] == p
+            if clip > 0:
+                yt[m] = np.minimum(yt[m], yt[m].min() + clip)
             yt[m] -= yt[m].mean()
         H.hf_mlp_init(X.shape[1], 1000 * (seed + f), members=members)
         train_loss.append(H.hf_mlp_train(X[keep], yt, epochs=epochs, lr=lr))
