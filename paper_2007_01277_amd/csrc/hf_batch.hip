@@ -472,7 +472,15 @@ static int batch_create(const hf_task* tasks, int ntask, const int32_t* group_of
       const int64_t by_bytes = std::max<int64_t>(1, (int64_t)(est_cost_us(&tasks[i]) * 5.0e6 / item_bytes));
       nvwg[i] = (uint32_t)std::max<int64_t>(1, std::min<int64_t>(useful_wgs(&tasks[i], dts[i], iw), by_bytes));
     }
+    // groups in order of decreasing work, so that the launch ends on short items
+    std::vector<int> gorder(ngroup);
+    std::vector<double> gcost(ngroup, 0.0);
     for (int g = 0; g < ngroup; ++g) {
+      gorder[g] = g;
+      for (int i = first[g]; i < first[g + 1]; ++i) gcost[g] += est_cost_us(&tasks[i]);
+    }
+    std::stable_sort(gorder.begin(), gorder.end(), [&](int x, int y) { return gcost[x] > gcost[y]; });
+    for (int g : gorder) {
       uint32_t most = 0;
       for (int i = first[g]; i < first[g + 1]; ++i) most = std::max(most, nvwg[i]);
       for (uint32_t b = 0; b < most; ++b)
