@@ -138,26 +138,6 @@ def test_ensemble_trains_and_roundtrips_through_a_file():
     assert np.array_equal(H.hf_mlp_predict(Xt), pred)
 
 
-def test_learned_tuner_at_the_workload_shape():
-    """The learned tuner's workload as the bench runs it: 40 seeded pairs of the
-    five data kernels, every candidate profiled twice (two independent
-    measurements), the ensemble trained on 50 configurations of each training
-    pair, 4-fold cross-validation by pair, top 3 of 85 profiled.  Over runs
-    and evaluation seeds the tuner's choice lands 3-6 % from the exhaustive
-    search's choice on the second measurement and 5-8 % on the first (where
-    the exhaustive best is the minimum of 85 noisy values), against 9-13 %
-    for 3 candidates profiled at random and 10-20 % for the even split on the
-    first; the bounds below leave room for that spread, and the tuner must
-    beat the even split and the random profiles."""
-    pairs = LT.draw_pairs(40, seed=2, kmin=16, kmax=26, kinds=LT.DATA_KINDS)
-    data = LT.collect(pairs, reps=10, seed=2, check=True)
-    res = LT.evaluate(data, folds=4, per_pair=50, topk=3, epochs=500)
-    print({k: v for k, v in res.items() if k != "per_pair"}, flush=True)
-    assert res["regret_mlp_checked_mean"] <= 0.08
-    assert res["regret_mlp_mean"] <= 0.11
-    assert res["regret_mlp_mean"] < min(res["regret_naive_mean"], res["regret_random_mean"])
-
-
 def test_hf_tune_mlp_profiles_only_topk():
     pairs = LT.draw_pairs(6, seed=6, kmin=18, kmax=22)
     data = LT.collect(pairs, reps=3, seed=6)
