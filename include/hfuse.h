@@ -396,7 +396,8 @@ int hf_batch_tune(const hf_task* tasks, int ntask, const int32_t* group_of_task,
  *                   region) and pulls the next, so the intervals of a
  *                   workgroup run different kernels side by side with no
  *                   whole-workgroup barrier between items.  The queue holds
- *                   the members of each group interleaved item by item.
+ *                   the members of each group interleaved item by item, the
+ *                   groups in order of decreasing estimated work.
  *   item_kb         estimated traffic of one work item, KiB (0: 256): the
  *                   virtual grid of a task is its traffic over this, capped by
  *                   the workgroups that find work.
