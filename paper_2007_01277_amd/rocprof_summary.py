@@ -143,6 +143,31 @@ def read_pmc(d):
     return res
 
 
+def clock_rows(d, xcds=8, simds=1024, min_ns=100000):
+    """{kernel name: (dispatches, median clock GHz, median VALU instructions per
+    SIMD per cycle)} from a --pmc pass that collected GRBM_GUI_ACTIVE (summed
+    over the XCDs) and SQ_INSTS_VALU: clock = GRBM_GUI_ACTIVE / xcds /
+    dispatch duration (its start and end timestamps in the same CSV).
+    Dispatches shorter than min_ns are left out (the busy count then spans
+    more than the kernel)."""
+    per = {}
+    for root, _, files in os.walk(d):
+        for f in files:
+            if f.endswith("counter_collection.csv"):
+                for r in csv.DictReader(open(os.path.join(root, f))):
+                    k = (r["Kernel_Name"], r["Dispatch_Id"])
+                    e = per.setdefault(k, {"ns": int(r["End_Timestamp"]) - int(r["Start_Timestamp"])})
+                    e[r["Counter_Name"]] = float(r["Counter_Value"])
+    out = {}
+    for (name, _), e in per.items():
+        if e["ns"] < min_ns or "GRBM_GUI_ACTIVE" not in e:
+            continue
+        cyc = e["GRBM_GUI_ACTIVE"] / xcds
+        out.setdefault(name, []).append((cyc / e["ns"], e.get("SQ_INSTS_VALU", 0.0) / (cyc * simds)))
+    return {n: (len(v), statistics.median(x[0] for x in v), statistics.median(x[1] for x in v))
+            for n, v in out.items()}
+
+
 def pick(res, match):
     """Kernel names matching `match`: alternatives separated by '|', each a
     list of substrings separated by '&' that must all occur."""
@@ -202,6 +227,15 @@ def counters(a):
         data = json.load(open(path)) if os.path.exists(path) else {}
         data[a.key] = entry
         json.dump(data, open(path, "w"), indent=1, sort_keys=True)
+    if a.clock:
+        lines += ["", "Clock and VALU issue per dispatch (GRBM_GUI_ACTIVE / 8 XCDs / dispatch duration; "
+                      "SQ_INSTS_VALU per SIMD per cycle; medians over dispatches of at least 100 us):", "",
+                  "| kernel | dispatches | clock GHz | VALU instructions / SIMD / cycle |", "|---|---:|---:|---:|"]
+        for d in a.dir:
+            rows = clock_rows(d)
+            for n in pick(rows, a.match):
+                k, ghz, ipc = rows[n]
+                lines.append(f"| `{short(n)}` | {k} | {ghz:.3f} | {ipc:.4f} |")
     if a.note:
         lines += ["", a.note]
     open(a.out, "w").write("\n".join(lines) + "\n")
@@ -269,6 +303,7 @@ def main():
     c.add_argument("--trace-csv", default="", help="kernel-trace stats CSV giving the solo durations")
     c.add_argument("--trace-dispatch", default="",
                    help="per-dispatch kernel trace CSV: solo durations from the launches that ran alone")
+    c.add_argument("--clock", action="store_true", help="also derive clock and VALU issue per cycle")
     c.add_argument("--cmd", required=True)
     c.add_argument("--out", required=True)
     c.add_argument("--title", default="")

@@ -61,3 +61,22 @@ def test_alone_by_grid_groups_dispatches_by_grid(tmp_path):
                  "".join(f"{n},{s},{e},{g}\n" for n, s, e, g in rows))
     res = RS.alone_by_grid_us(str(f), "K")
     assert res == {64: (2, 0.01, 0.01), 128: (1, 0.006, 0.006)}
+
+
+def test_clock_rows_derive_clock_and_issue_rate(tmp_path):
+    """GRBM_GUI_ACTIVE summed over 8 XCDs over a 1 ms dispatch of 2.4e6 cycles
+    per XCD is 2.4 GHz; 0.25 instructions per SIMD per cycle over 1024 SIMDs
+    is 0.25 * 1024 * 2.4e6 VALU instructions.  A 10 us dispatch is left out."""
+    hdr = "Dispatch_Id,Kernel_Name,Counter_Name,Counter_Value,Start_Timestamp,End_Timestamp\n"
+    rows = [
+        "1,kern,GRBM_GUI_ACTIVE,%d,0,1000000" % (8 * 2400000),
+        "1,kern,SQ_INSTS_VALU,%d,0,1000000" % int(0.25 * 1024 * 2400000),
+        "2,kern,GRBM_GUI_ACTIVE,%d,2000000,3000000" % (8 * 2200000),
+        "2,kern,SQ_INSTS_VALU,%d,2000000,3000000" % int(0.25 * 1024 * 2200000),
+        "3,short,GRBM_GUI_ACTIVE,999999,5000000,5010000",
+    ]
+    (tmp_path / "pmc_counter_collection.csv").write_text(hdr + "\n".join(rows) + "\n")
+    res = RS.clock_rows(str(tmp_path))
+    assert set(res) == {"kern"}
+    n, ghz, ipc = res["kern"]
+    assert n == 2 and ghz == pytest.approx(2.3) and ipc == pytest.approx(0.25)
