@@ -77,7 +77,7 @@ def _load():
         lib.oracle_upsample_absmag.restype = ctypes.c_int
         lib.oracle_maxpool.argtypes = [P, I64, I64, I64, I64, I32, I32, I32, I32, P, P]
         lib.oracle_maxpool.restype = ctypes.c_int
-        lib.oracle_ethash_like.argtypes = [P, ctypes.c_uint32, I64, P, I64, P]
+        lib.oracle_ethash_like.argtypes = [P, I64, P, I64, P]
         lib.oracle_ethash_like.restype = ctypes.c_int
         _libs[path] = lib
     return lib
@@ -173,12 +173,15 @@ def maxpool(x: np.ndarray, kh: int, kw: int, stride: int, pad: int):
 
 def ethash_like(header: bytes, nonce0: int, table: np.ndarray, n: int) -> np.ndarray:
     """Digests [n][32] (uint8) of the Ethash-like walk over `table` [rows][32]
-    uint32 (the C transcription of the definition in hashes.py)."""
-    hdr = np.frombuffer(bytes(header), np.uint8)
-    assert hdr.size == 80
+    uint32: the seeds from hashes.ethash_seed (SHA-512 by hashlib), the walk
+    and the fold by the C transcription of the definition in hashes.py."""
+    from . import hashes
+    assert len(header) == 80
+    seeds = np.array([hashes.ethash_seed(hashes.message(bytes(header), nonce0 + i)) for i in range(n)],
+                     np.uint32).reshape(n, 16)
     table = np.ascontiguousarray(table, dtype=np.uint32)
     out = np.empty((n, 32), np.uint8)
-    rc = _load().oracle_ethash_like(_ptr(hdr), nonce0 & 0xFFFFFFFF, n, _ptr(table), table.shape[0], _ptr(out))
+    rc = _load().oracle_ethash_like(_ptr(seeds), n, _ptr(table), table.shape[0], _ptr(out))
     if rc != 0:
         raise ValueError("bad Ethash-like parameters")
     return out

@@ -22,27 +22,33 @@ nonce0 + i (mod 2^32); each instance outputs a 32-byte digest.
     definition (2.6: the SHA-512 initial value, i.e. the first 64 fractional
     bits of the square roots of the first 8 primes).  The message schedule
     SIGMA (2.7) is a table of the RFC, typed here.
-  * ethash_like : not Ethash itself (no Keccak, synthetic table), but the shape
-    of its inner loop: a 32-word mix is folded with 64 pseudo-random 128-byte
-    table rows, the row of access i chosen from the mix, by the FNV step
-    fnv(a, b) = (a * 16777619) ^ b (mod 2^32).  Definition used here:
+  * ethash_like : not Ethash itself (synthetic table, SHA-512 in place of
+    Keccak-512), but the shape of its hashimoto loop: a 512-bit seed hash of
+    the message, repeated into a 32-word mix that is folded with 64
+    pseudo-random 128-byte table rows, the row of access i chosen from the
+    mix, by the FNV step fnv(a, b) = (a * 16777619) ^ b (mod 2^32).
+    Definition used here:
       msg = the 80-byte message of the instance (header[0:76] || le32(nonce));
-      s[0] = FNV-1 (32 bits) of the 80 bytes of msg;
-      s[k] = fnv(s[k-1], k) for k = 1..15, i.e. s[k] is FNV-1 of msg followed
-             by the bytes 1, 2, ..., k;  mix[j] = s[j mod 16];
+      s[0..15] = SHA-512(msg) (FIPS 180-4, the library's) read as sixteen
+                 little-endian 32-bit words, where Ethash reads its Keccak-512
+                 seed the same way;  mix[j] = s[j mod 16];
       for i in 0..63: p = fnv(i ^ s[0], mix[i mod 32]) mod R;
                       mix[j] = fnv(mix[j], T[p][j]) for j in 0..31;
       out[k] = fnv(fnv(fnv(mix[4k], mix[4k+1]), mix[4k+2]), mix[4k+3]), k < 8;
       digest = out[0..7] as little-endian bytes.
     The row of access i is Ethash's own access formula (its hashimoto loop)
-    with the table's row count in place of the dataset's page count.
-    Pins: the FNV step and the seed chain against the published FNV-1 test
-    values (s[k] is FNV-1 of a byte string), the all-zero-table closed form
-    of the 64 folds and of the final 4-to-1 fold, and which rows the
-    computation depends on.  The access formula itself is a stated reading
-    (Ethash's), checked only through those dependence tests.
+    with the table's row count in place of the dataset's page count; Ethash
+    hashes the seed and the folded mix once more with Keccak-256, which is
+    left out here (the fold is the digest).
+    Pins: the seed is hashlib's SHA-512; the FNV step against the published
+    FNV-1 test values; the all-zero-table closed form of the 64 folds and of
+    the final 4-to-1 fold; the nonce's little-endian placement; which rows
+    the computation depends on.  The access formula itself is a stated
+    reading (Ethash's), checked only through those dependence tests.
 """
 from __future__ import annotations
+
+import hashlib
 
 M32 = 0xFFFFFFFF
 M64 = 0xFFFFFFFFFFFFFFFF
@@ -229,17 +235,19 @@ def fnv1_32(data: bytes) -> int:
     return h
 
 
+def ethash_seed(msg: bytes) -> list:
+    """The 16 seed words of a message: its SHA-512 digest (FIPS 180-4, computed
+    by hashlib) read as little-endian 32-bit words."""
+    d = hashlib.sha512(msg).digest()
+    return [int.from_bytes(d[4 * k: 4 * k + 4], "little") for k in range(16)]
+
+
 def ethash_like_one(header: bytes, nonce: int, table, rows_accessed=None) -> bytes:
     """One instance of the definition in this module's docstring.  `table` is a
     sequence of R rows of 32 uint32 words; `rows_accessed`, if a list, receives
     the 64 row indices in access order."""
     R = len(table)
-    h = FNV_OFFSET
-    for byte in message(header, nonce):
-        h = fnv(h, byte)
-    s = [h]
-    for k in range(1, 16):
-        s.append(fnv(s[k - 1], k))
+    s = ethash_seed(message(header, nonce))
     mix = [s[j % 16] for j in range(32)]
     for i in range(64):
         p = fnv(i ^ s[0], mix[i % 32]) % R

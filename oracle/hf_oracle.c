@@ -269,28 +269,21 @@ OR_EXPORT int oracle_maxpool(const float* x, int64_t N, int64_t C, int64_t H, in
 
 /* --------------------------------------------------------------- Ethash-like */
 /* The Ethash-like walk written out in C for the full-size checks; the same
- * definition as oracle/hashes.py (the tests check the two against each other):
- * msg = header[0:76] || le32(nonce0 + i);  s0 = FNV-1 of the 80 bytes of msg;
- * s_k = fnv(s_(k-1), k);  mix_j = s_(j mod 16);  for a = 0..63:
- * p = fnv(a ^ s0, mix_(a mod 32)) mod rows, mix_j = fnv(mix_j, T[p][j]);
- * out_k = fnv(fnv(fnv(mix_4k, mix_4k+1), mix_4k+2), mix_4k+3), as 8
- * little-endian words per instance. */
+ * definition as oracle/hashes.py (the tests check the two against each other).
+ * The seeds come in from the caller: seeds[16 i .. 16 i + 15] are the sixteen
+ * little-endian words of SHA-512 of instance i's message.  mix_j = s_(j mod 16);
+ * for a = 0..63: p = fnv(a ^ s0, mix_(a mod 32)) mod rows,
+ * mix_j = fnv(mix_j, T[p][j]);  out_k = fnv(fnv(fnv(mix_4k, mix_4k+1),
+ * mix_4k+2), mix_4k+3), as 8 little-endian words per instance. */
 static uint32_t fnv32(uint32_t a, uint32_t b) { return (a * 16777619u) ^ b; }
 
-OR_EXPORT int oracle_ethash_like(const uint8_t* header, uint32_t nonce0, int64_t n,
-                                 const uint32_t* table, int64_t rows, uint8_t* out) {
+OR_EXPORT int oracle_ethash_like(const uint32_t* seeds, int64_t n, const uint32_t* table, int64_t rows,
+                                 uint8_t* out) {
   if (rows < 1 || n < 0) return -1;
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; ++i) {
-    uint8_t msg[80];
-    memcpy(msg, header, 76);
-    const uint32_t nonce = nonce0 + (uint32_t)i;
-    for (int b = 0; b < 4; ++b) msg[76 + b] = (uint8_t)(nonce >> (8 * b));
-    uint32_t s[16], mix[32];
-    uint32_t h = 2166136261u;
-    for (int b = 0; b < 80; ++b) h = fnv32(h, msg[b]);
-    s[0] = h;
-    for (int k = 1; k < 16; ++k) s[k] = fnv32(s[k - 1], (uint32_t)k);
+    const uint32_t* s = seeds + 16 * i;
+    uint32_t mix[32];
     for (int j = 0; j < 32; ++j) mix[j] = s[j % 16];
     for (uint32_t a = 0; a < 64; ++a) {
       const uint64_t p = (uint64_t)fnv32(a ^ s[0], mix[a % 32]) % (uint64_t)rows;

@@ -1,7 +1,8 @@
 """Pins of the hash oracles (oracle/hashes.py) against what does not come from
 them: the worked examples and constants printed in FIPS 180-4 and RFC 7693,
 the published FNV-1 test values, an independent implementation (hashlib), and
-closed forms and dependence checks of the Ethash-like loop."""
+closed forms and dependence checks of the Ethash-like loop (whose seed is
+hashlib's SHA-512 of the message)."""
 import hashlib
 import os
 
@@ -87,42 +88,64 @@ def _table(R, seed):
     return inputs.rng(seed).integers(0, 2 ** 32, size=(R, 32), dtype=np.uint64).astype(np.uint32)
 
 
+def _fold8(mix):
+    out = []
+    for k in range(8):
+        a = mix[4 * k]
+        for t in range(1, 4):
+            a = ((a * 16777619) % 2 ** 32) ^ mix[4 * k + t]
+        out.append(a)
+    return out
+
+
 def test_ethash_like_zero_table_closed_form():
     # With an all-zero table every access multiplies each mix word by the FNV
     # prime, whatever rows are read: mix_j = s_(j mod 16) * P^64, then the
-    # 4-to-1 fold.  The seeds come from fnv1_32, the byte-wise FNV-1 that the
-    # published test values pin: s_k is FNV-1 of the instance's 80-byte
-    # message followed by the bytes 1..k.
+    # 4-to-1 fold.  The seed words are SHA-512 of the instance's 80-byte
+    # message, read here as little-endian words by numpy.
     hdr = bytes(inputs.rng(8).integers(0, 256, size=80, dtype=np.uint8))
+    p64 = pow(16777619, 64, 2 ** 32)
     for nonce in (99, 0xFFFFFFFF, 0x01020304):
         msg = hdr[:76] + nonce.to_bytes(4, "little")
-        s = [O.fnv1_32(msg + bytes(range(1, k + 1))) for k in range(16)]
-        p64 = pow(16777619, 64, 2 ** 32)
-        mix = [(s[j % 16] * p64) % 2 ** 32 for j in range(32)]
-        out = []
-        for k in range(8):
-            a = mix[4 * k]
-            for t in range(1, 4):
-                a = ((a * 16777619) % 2 ** 32) ^ mix[4 * k + t]
-            out.append(a)
-        want = b"".join(v.to_bytes(4, "little") for v in out)
+        s = np.frombuffer(hashlib.sha512(msg).digest(), "<u4").astype(int)
+        mix = [(int(s[j % 16]) * p64) % 2 ** 32 for j in range(32)]
+        want = np.array(_fold8(mix), "<u4").tobytes()
         assert O.ethash_like_one(hdr, nonce, np.zeros((37, 32), np.uint32)) == want
 
 
 def test_ethash_like_seed_takes_every_nonce_byte_little_endian():
     # Nonces on both sides of each byte carry: under the zero-table closed form
-    # the first digest word is the fold of s_0..s_3 * P^64, and s_k is FNV-1 of
-    # the message with the nonce's four bytes in little-endian order.
+    # the digest is a function of SHA-512 of the message with the nonce's four
+    # bytes in little-endian order, and of nothing else.
     hdr = bytes(range(80))
     p64 = pow(16777619, 64, 2 ** 32)
     for nonce in (0xFF, 0x100, 0xFFFF, 0x10000, 0xFFFFFF, 0x1000000):
         msg = hdr[:76] + bytes([nonce & 0xFF, (nonce >> 8) & 0xFF, (nonce >> 16) & 0xFF, nonce >> 24])
-        mix = [(O.fnv1_32(msg + bytes(range(1, k + 1))) * p64) % 2 ** 32 for k in range(4)]
-        a = mix[0]
-        for t in range(1, 4):
-            a = ((a * 16777619) % 2 ** 32) ^ mix[t]
+        s = np.frombuffer(hashlib.sha512(msg).digest(), "<u4").astype(int)
+        mix = [(int(s[j % 16]) * p64) % 2 ** 32 for j in range(32)]
         got = O.ethash_like_one(hdr, nonce, np.zeros((1, 32), np.uint32))
-        assert int.from_bytes(got[:4], "little") == a, hex(nonce)
+        assert got == np.array(_fold8(mix), "<u4").tobytes(), hex(nonce)
+
+
+def test_ethash_like_uses_all_sixteen_seed_words():
+    # A one-row table whose words all equal c: every access reads that row and
+    # maps each mix word x to x*P ^ c, so mix_j = g(s_(j mod 16)) with g those
+    # 64 maps composed, whatever the access rule; then the 4-to-1 fold.  Two
+    # nonces give seeds that differ in all 16 words, and digests that differ.
+    hdr = bytes(inputs.rng(14).integers(0, 256, size=80, dtype=np.uint8))
+    T = np.full((1, 32), 0x9E3779B9, np.uint32)
+    a = np.frombuffer(O.ethash_like_one(hdr, 1, T), "<u4")
+    b = np.frombuffer(O.ethash_like_one(hdr, 2, T), "<u4")
+    sa = np.frombuffer(hashlib.sha512(hdr[:76] + (1).to_bytes(4, "little")).digest(), "<u4")
+    sb = np.frombuffer(hashlib.sha512(hdr[:76] + (2).to_bytes(4, "little")).digest(), "<u4")
+    assert np.all(sa != sb) and np.all(a != b)
+    def g(x):
+        for _ in range(64):
+            x = ((x * 16777619) % 2 ** 32) ^ 0x9E3779B9
+        return x
+    for s, d in ((sa, a), (sb, b)):
+        mix = [g(int(s[j % 16])) for j in range(32)]
+        assert list(d) == _fold8(mix)
 
 
 def test_ethash_like_depends_exactly_on_the_rows_it_reads():
