@@ -68,7 +68,7 @@ typedef enum {
   HF_MAXPOOL = 5,   /* 2-D max pooling with the winner's flat index (Sec. IV-A)      */
   HF_SHA256D = 6,   /* SHA-256(SHA-256(header with nonce)), FIPS 180-4               */
   HF_BLAKE2B = 7,   /* BLAKE2b, 32-byte digest, no key, of header with nonce, RFC 7693 */
-  HF_ETHASH = 8,    /* Ethash-like: 64 FNV folds of random 128-byte table rows        */
+  HF_ETHASH = 8,    /* Ethash-like: SHA-512 seed, 64 FNV folds of random table rows  */
   HF_NUM_KINDS = 9
 } hf_kind;
 
@@ -109,10 +109,10 @@ typedef enum {
  *                SHA256D, BLAKE2B, ETHASH: p[0] = first nonce (as uint32)
  *   in1          ETHASH: the table, uint32 [h][32] (h rows of 128 bytes,
  *                16-byte aligned, 1 <= h < 2^32); unused (NULL) otherwise.
- *                The seed s0 of a hash is FNV-1 (32 bits) of its 80-byte
- *                message, s_k = fnv(s_(k-1), k) for k = 1..15 and the mix
- *                starts as s_(j mod 16); the row of access j is
- *                fnv(j ^ s0, mix[j % 32]) % h, with
+ *                The seed words s_0..s_15 of a hash are SHA-512 (FIPS 180-4)
+ *                of its 80-byte message read as little-endian 32-bit words,
+ *                the mix starts as s_(j mod 16), and the row of access j is
+ *                fnv(j ^ s_0, mix[j % 32]) % h, with
  *                fnv(a, b) = (a * 16777619) ^ b mod 2^32 (Ethash's access rule).
  * Input and output buffers must be 4-byte aligned (LDS_HIST input: any) and must
  * not overlap.  Element counts must stay below 2^31 per buffer. */

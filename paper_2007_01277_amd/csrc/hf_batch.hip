@@ -258,7 +258,7 @@ static double est_cost_us(const hf_task* t) {
     }
     case HF_SHA256D: bytes = 32 * n; ops = 3 * 64 * 24.0 * n; break;  // 3 compressions of ~24 ops/round
     case HF_BLAKE2B: bytes = 32 * n; ops = 12 * 8 * 28.0 * n; break;  // 12 rounds of 8 G of ~28 ops
-    case HF_ETHASH: bytes = (64 * 128.0 + 32) * n; ops = 64 * 40.0 * n / 8; break;  // latency-bound rows
+    case HF_ETHASH: bytes = (64 * 128.0 + 32) * n; ops = (64 * 40.0 / 8 + 80 * 55.0) * n; break;  // rows + SHA-512
   }
   return std::max(bytes / 5.0e6, ops / 38.0e6);  // us at ~5 TB/s and ~38 T lane-op/s
 }

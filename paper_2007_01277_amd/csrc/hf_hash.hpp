@@ -11,6 +11,32 @@
 
 namespace hf {
 
+// 64-bit rotate and shift right by a compile-time amount (SHA-512).  A value
+// that differs between lanes (uni false) takes one funnel shift
+// (v_alignbit_b32) per 32-bit half, where the compiler's own lowering of a
+// 64-bit rotate takes two 64-bit shifts and two ORs.  A wave-uniform value (uni
+// true) keeps the plain form, which the scalar unit executes: the alignbit form
+// exists only as a vector instruction and would move uniform work, and the
+// registers that hold its results across the loop, to the vector unit.
+__device__ __forceinline__ uint64_t rotr64(uint64_t x, uint32_t n, bool uni = false) {
+  if (uni) return __builtin_rotateright64(x, n);
+  const uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
+  uint32_t rl, rh;
+  if (n < 32) {
+    rl = __builtin_amdgcn_alignbit(hi, lo, n);
+    rh = __builtin_amdgcn_alignbit(lo, hi, n);
+  } else {
+    rl = __builtin_amdgcn_alignbit(lo, hi, n - 32);
+    rh = __builtin_amdgcn_alignbit(hi, lo, n - 32);
+  }
+  return ((uint64_t)rh << 32) | rl;
+}
+__device__ __forceinline__ uint64_t shr64(uint64_t x, uint32_t n, bool uni = false) {  // 0 < n < 32
+  if (uni) return x >> n;
+  const uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
+  return ((uint64_t)(hi >> n) << 32) | __builtin_amdgcn_alignbit(hi, lo, n);
+}
+
 // ============================================================ SHA-256d
 // FIPS 180-4.  The first 64 header bytes are the same for every nonce, so their
 // compression (the midstate) is computed once per wavefront from uniform
@@ -216,88 +242,222 @@ struct Blake2b {
   }
 };
 
+// ============================================================ SHA-512
+// FIPS 180-4, the seed hash of the Ethash-like walk.  An 80-byte message is one
+// padded 128-byte block (Sec. 5.1.2): message words 0..9, then 2^63, four zero
+// words and the bit length 640.  Words 0..8 do not depend on the nonce, so the
+// caller runs rounds 0..8 once per wavefront on uniform values.
+struct Sha512 {
+  // Sec. 4.2.3: round constants
+  static constexpr uint64_t kK[80] = {
+      0x428a2f98d728ae22ull, 0x7137449123ef65cdull, 0xb5c0fbcfec4d3b2full, 0xe9b5dba58189dbbcull,
+      0x3956c25bf348b538ull, 0x59f111f1b605d019ull, 0x923f82a4af194f9bull, 0xab1c5ed5da6d8118ull,
+      0xd807aa98a3030242ull, 0x12835b0145706fbeull, 0x243185be4ee4b28cull, 0x550c7dc3d5ffb4e2ull,
+      0x72be5d74f27b896full, 0x80deb1fe3b1696b1ull, 0x9bdc06a725c71235ull, 0xc19bf174cf692694ull,
+      0xe49b69c19ef14ad2ull, 0xefbe4786384f25e3ull, 0x0fc19dc68b8cd5b5ull, 0x240ca1cc77ac9c65ull,
+      0x2de92c6f592b0275ull, 0x4a7484aa6ea6e483ull, 0x5cb0a9dcbd41fbd4ull, 0x76f988da831153b5ull,
+      0x983e5152ee66dfabull, 0xa831c66d2db43210ull, 0xb00327c898fb213full, 0xbf597fc7beef0ee4ull,
+      0xc6e00bf33da88fc2ull, 0xd5a79147930aa725ull, 0x06ca6351e003826full, 0x142929670a0e6e70ull,
+      0x27b70a8546d22ffcull, 0x2e1b21385c26c926ull, 0x4d2c6dfc5ac42aedull, 0x53380d139d95b3dfull,
+      0x650a73548baf63deull, 0x766a0abb3c77b2a8ull, 0x81c2c92e47edaee6ull, 0x92722c851482353bull,
+      0xa2bfe8a14cf10364ull, 0xa81a664bbc423001ull, 0xc24b8b70d0f89791ull, 0xc76c51a30654be30ull,
+      0xd192e819d6ef5218ull, 0xd69906245565a910ull, 0xf40e35855771202aull, 0x106aa07032bbd1b8ull,
+      0x19a4c116b8d2d0c8ull, 0x1e376c085141ab53ull, 0x2748774cdf8eeb99ull, 0x34b0bcb5e19b48a8ull,
+      0x391c0cb3c5c95a63ull, 0x4ed8aa4ae3418acbull, 0x5b9cca4f7763e373ull, 0x682e6ff3d6b2b8a3ull,
+      0x748f82ee5defb2fcull, 0x78a5636f43172f60ull, 0x84c87814a1f0ab72ull, 0x8cc702081a6439ecull,
+      0x90befffa23631e28ull, 0xa4506cebde82bde9ull, 0xbef9a3f7b2c67915ull, 0xc67178f2e372532bull,
+      0xca273eceea26619cull, 0xd186b8c721c0c207ull, 0xeada7dd6cde0eb1eull, 0xf57d4f7fee6ed178ull,
+      0x06f067aa72176fbaull, 0x0a637dc5a2c898a6ull, 0x113f9804bef90daeull, 0x1b710b35131c471bull,
+      0x28db77f523047d84ull, 0x32caab7b40c72493ull, 0x3c9ebe0a15c9bebcull, 0x431d67c49c100d4cull,
+      0x4cc5d4becb3e42b6ull, 0x597f299cfc657e2aull, 0x5fcb6fab3ad6faecull, 0x6c44198c4a475817ull};
+  // Sec. 5.3.5: the initial hash value, which BLAKE2b takes as its IV
+  __device__ static __forceinline__ uint64_t h0(int k) { return Blake2b::kIV[k]; }
+
+  // Which words of the schedule of an 80-byte message with a varying word 9
+  // are the same in every lane: the header words 0..8, the padding words
+  // 10..15, and the schedule words 17, 19 and 21, whose four inputs all are.
+  // It only picks the instruction form of a rotate (above), never the value.
+  __device__ static constexpr bool uni(int j) {
+    return j <= 8 || (j >= 10 && j <= 15) || j == 17 || j == 19 || j == 21;
+  }
+
+  // Sec. 6.4.2, rounds T0 .. T1-1 on the working variables v; w is the rolling
+  // 16-word schedule (rounds below 16 read the block itself).  Every index is a
+  // compile-time constant once the loop is unrolled.  Rounds below 9 see only
+  // uniform values (the caller runs them once per wavefront).  The uniform
+  // terms of a schedule word are summed first and with the round constant, so
+  // that they form one loop-invariant value.
+  template <int T0, int T1>
+  __device__ static __forceinline__ void rounds(uint64_t (&v)[8], uint64_t (&w)[16]) {
+    uint64_t a = v[0], b = v[1], c = v[2], d = v[3], e = v[4], f = v[5], g = v[6], h = v[7];
+#pragma unroll
+    for (int t = T0; t < T1; ++t) {
+      const bool us = t < 9;  // the state is uniform
+      uint64_t ku, wv;        // round constant plus the uniform part of W_t; the rest
+      if (t < 16) {
+        ku = uni(t) ? kK[t] + w[t] : kK[t];
+        wv = uni(t) ? 0 : w[t];
+      } else {
+        const int i = t & 15;
+        const uint64_t x = w[(i + 1) & 15], y = w[(i + 14) & 15];
+        const bool ux = uni(t - 15), uy = uni(t - 2);
+        const uint64_t s0 = rotr64(x, 1, ux) ^ rotr64(x, 8, ux) ^ shr64(x, 7, ux);
+        const uint64_t s1 = rotr64(y, 19, uy) ^ rotr64(y, 61, uy) ^ shr64(y, 6, uy);
+        const uint64_t q = w[(i + 9) & 15], r = w[i];
+        const bool uq = uni(t - 7), ur = uni(t - 16);
+        const uint64_t wu = (uy ? s1 : 0) + (uq ? q : 0) + (ux ? s0 : 0) + (ur ? r : 0);
+        wv = (uy ? 0 : s1) + (uq ? 0 : q) + (ux ? 0 : s0) + (ur ? 0 : r);
+        ku = kK[t] + wu;
+        w[i] = wu + wv;
+      }
+      const uint64_t S1 = rotr64(e, 14, us) ^ rotr64(e, 18, us) ^ rotr64(e, 41, us);
+      const uint64_t ch = (e & f) ^ (~e & g);
+      const uint64_t T1v = ku + h + S1 + ch + wv;
+      const uint64_t S0 = rotr64(a, 28, us) ^ rotr64(a, 34, us) ^ rotr64(a, 39, us);
+      const uint64_t ab = a ^ b, maj = (ab & c) | (~ab & a);  // a where a == b, else c
+      h = g;
+      g = f;
+      f = e;
+      e = d + T1v;
+      d = c;
+      c = b;
+      b = a;
+      a = T1v + S0 + maj;
+    }
+    v[0] = a;
+    v[1] = b;
+    v[2] = c;
+    v[3] = d;
+    v[4] = e;
+    v[5] = f;
+    v[6] = g;
+    v[7] = h;
+  }
+};
+
 // ============================================================ Ethash-like
-// The inner loop of Ethash over a synthetic table: a 32-word mix folded with
-// 64 table rows of 128 bytes, each row chosen from the mix.  Eight lanes carry
-// one hash: lane g of the group holds mix words 4g..4g+3, so a row is read as
-// one contiguous 128-byte segment (a 16-byte load per lane) and the word that
-// picks the next row is broadcast within the group with a lane permute.  Each
-// group carries kChains independent hashes whose row reads are issued back to
-// back, so every wavefront keeps 8 * kChains reads in flight per step.  Lanes
-// of a group past the last instance redo the last instance and store nothing,
-// so every lane takes part in every permute.
+// Ethash's hashimoto loop over a synthetic table, with SHA-512 of the message
+// as the 512-bit seed: a 32-word mix (the seed words twice) folded with 64
+// table rows of 128 bytes, each row chosen from the mix.  Every lane first
+// hashes the message of one instance (64 instances per wavefront and
+// iteration, rounds 0..8 hoisted as uniform work).  The walks then run in two
+// passes of 32 instances: eight lanes carry one walk, lane g of the group
+// holding mix words 4g..4g+3, so a row is read as one contiguous 128-byte
+// segment (a 16-byte load per lane), and the word that picks the next row is
+// broadcast within the group with a lane permute.  Each group carries kChains
+// walks whose row reads are issued back to back, so every wavefront keeps
+// 8 * kChains reads in flight per step.  Lanes past the last instance redo
+// the last instance and store nothing, so every lane takes part in every
+// permute.
 struct EthashLike {
   static constexpr uint32_t lds_words(int) { return 0; }
   static constexpr uint32_t kPrime = 16777619u;
-  static constexpr uint32_t kOffset = 2166136261u;
   static constexpr uint32_t kChains = 4;
-  static constexpr uint32_t kPerWave = 8 * kChains;  // hashes per wavefront per step
+  static constexpr uint32_t kPerPass = 8 * kChains;  // walks per wavefront per pass
+  static constexpr uint32_t kPerIter = 64;            // seeds per wavefront per iteration
 
   __device__ static __forceinline__ uint32_t fnv(uint32_t x, uint32_t y) { return (x * kPrime) ^ y; }
+
+  // the big-endian 64-bit message word k of the header (bytes 8k .. 8k+7)
+  __device__ static __forceinline__ uint64_t hdr64(const uint32_t* hdr, int k) {
+    return ((uint64_t)__builtin_bswap32(hdr[2 * k]) << 32) | __builtin_bswap32(hdr[2 * k + 1]);
+  }
 
   template <class Bar>
   __device__ static void run(const DevTask& dt, const Part& p, Bar&, uint32_t*) {
     const EthArgs& a = dt.eth;
     if (a.n == 0) return;
-    // FNV-1 over the 76 header bytes that every instance shares: uniform
-    uint32_t h76 = kOffset;
+    // rounds 0..8 read header words only: uniform, so scalar registers
+    uint64_t w0[16], mid[8];
 #pragma unroll
-    for (int k = 0; k < 19; ++k) {
-      const uint32_t w = a.hdr[k];
+    for (int k = 0; k < 16; ++k) w0[k] = k < 9 ? hdr64(a.hdr, k) : 0;
 #pragma unroll
-      for (int b = 0; b < 4; ++b) h76 = fnv(h76, (w >> (8 * b)) & 0xFFu);
-    }
-    h76 = uniform(h76);
+    for (int k = 0; k < 8; ++k) mid[k] = Sha512::h0(k);
+    Sha512::rounds<0, 9>(mid, w0);
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      mid[k] = ((uint64_t)uniform((uint32_t)(mid[k] >> 32)) << 32) | uniform((uint32_t)mid[k]);
+    const uint64_t w9hi = (uint64_t)__builtin_bswap32(a.hdr[18]) << 32;
     const uint32_t lane = lane_id();
     const uint32_t grp = lane >> 3, gl = lane & 7u, q = gl & 3u;
     const uint32_t gbase = lane & ~7u;
-    const uint32_t stride = kPerWave * p.nwg * p.nwaves;
-    for (uint32_t base = kPerWave * (p.wg * p.nwaves + p.wave); base < a.n; base += stride) {  // wave-uniform
-      uint32_t s0[kChains], mx[kChains][4];
+    const uint32_t stride = kPerIter * p.nwg * p.nwaves;
+    for (uint32_t base = kPerIter * (p.wg * p.nwaves + p.wave); base < a.n; base += stride) {  // wave-uniform
+      // this lane's seed: SHA-512 of instance base + lane, as 16 little-endian words
+      uint32_t sd[16];
+      {
+        uint64_t v[8], w[16];
 #pragma unroll
-      for (uint32_t h = 0; h < kChains; ++h) {
-        const uint32_t ic = min(base + 8u * h + grp, a.n - 1u);
-        const uint32_t nonce = a.nonce0 + ic;  // its four bytes, little-endian
-        s0[h] = fnv(fnv(fnv(fnv(h76, nonce & 0xFFu), (nonce >> 8) & 0xFFu), (nonce >> 16) & 0xFFu), nonce >> 24);
-        uint32_t s[16];
-        s[0] = s0[h];
+        for (int k = 0; k < 8; ++k) v[k] = mid[k];
 #pragma unroll
-        for (int k = 1; k < 16; ++k) s[k] = fnv(s[k - 1], (uint32_t)k);
-        // mix words 4*gl .. 4*gl+3 are s[(4*gl + c) % 16] = s[4*(gl % 4) + c]
+        for (int k = 0; k < 9; ++k) w[k] = w0[k];
+        w[9] = w9hi | __builtin_bswap32(a.nonce0 + min(base + lane, a.n - 1u));
+        w[10] = 0x8000000000000000ull;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          uint32_t v = s[c];
+        for (int k = 11; k < 15; ++k) w[k] = 0;
+        w[15] = 640;
+        Sha512::rounds<9, 16>(v, w);
+        Sha512::rounds<16, 32>(v, w);
+        Sha512::rounds<32, 48>(v, w);
+        Sha512::rounds<48, 64>(v, w);
+        Sha512::rounds<64, 80>(v, w);
 #pragma unroll
-          for (int r = 1; r < 4; ++r) v = (q == (uint32_t)r) ? s[4 * r + c] : v;
-          mx[h][c] = v;
+        for (int k = 0; k < 8; ++k) {
+          const uint64_t hk = Sha512::h0(k) + v[k];
+          sd[2 * k] = __builtin_bswap32((uint32_t)(hk >> 32));
+          sd[2 * k + 1] = __builtin_bswap32((uint32_t)hk);
         }
       }
+#pragma unroll 1
+      for (uint32_t pass = 0; pass < kPerIter / kPerPass; ++pass) {
+        const uint32_t pbase = base + kPerPass * pass;
+        if (pbase >= a.n) break;  // wave-uniform
+        // walk h of group grp is instance pbase + 8h + grp, whose seed lane
+        // kPerPass*pass + 8h + grp holds; lane g of the group takes mix words
+        // 4g..4g+3 = seed words 4(g % 4)..4(g % 4)+3, and every lane seed word 0
+        uint32_t s0[kChains], mx[kChains][4];
+#pragma unroll
+        for (uint32_t h = 0; h < kChains; ++h) {
+          const int src = (int)((kPerPass * pass + 8u * h + grp) << 2);
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            uint32_t v = 0;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const uint32_t t = (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)sd[4 * r + c]);
+              if (r == 0 && c == 0) s0[h] = t;
+              v = q == (uint32_t)r ? t : v;
+            }
+            mx[h][c] = v;
+          }
+        }
 #pragma unroll 4
-      for (uint32_t j = 0; j < 64; ++j) {
-        // mix word j % 32 is component j % 4 of lane (j % 32) / 4 of the group
-        const uint32_t cj = j & 3u;
-        const uint32_t src = (gbase + ((j & 31u) >> 2)) << 2;
-        uint4 d[kChains];
+        for (uint32_t j = 0; j < 64; ++j) {
+          // mix word j % 32 is component j % 4 of lane (j % 32) / 4 of the group
+          const uint32_t cj = j & 3u;
+          const uint32_t src = (gbase + ((j & 31u) >> 2)) << 2;
+          uint4 d[kChains];
 #pragma unroll
-        for (uint32_t h = 0; h < kChains; ++h) {
-          const uint32_t comp = cj == 0 ? mx[h][0] : (cj == 1 ? mx[h][1] : (cj == 2 ? mx[h][2] : mx[h][3]));
-          const uint32_t mw = (uint32_t)__builtin_amdgcn_ds_bpermute((int)src, (int)comp);
-          const uint32_t row = fnv(j ^ s0[h], mw) % a.rows;
-          d[h] = a.table[(size_t)row * 8u + gl];
+          for (uint32_t h = 0; h < kChains; ++h) {
+            const uint32_t comp = cj == 0 ? mx[h][0] : (cj == 1 ? mx[h][1] : (cj == 2 ? mx[h][2] : mx[h][3]));
+            const uint32_t mw = (uint32_t)__builtin_amdgcn_ds_bpermute((int)src, (int)comp);
+            const uint32_t row = fnv(j ^ s0[h], mw) % a.rows;
+            d[h] = a.table[(size_t)row * 8u + gl];
+          }
+#pragma unroll
+          for (uint32_t h = 0; h < kChains; ++h) {
+            mx[h][0] = fnv(mx[h][0], d[h].x);
+            mx[h][1] = fnv(mx[h][1], d[h].y);
+            mx[h][2] = fnv(mx[h][2], d[h].z);
+            mx[h][3] = fnv(mx[h][3], d[h].w);
+          }
         }
 #pragma unroll
         for (uint32_t h = 0; h < kChains; ++h) {
-          mx[h][0] = fnv(mx[h][0], d[h].x);
-          mx[h][1] = fnv(mx[h][1], d[h].y);
-          mx[h][2] = fnv(mx[h][2], d[h].z);
-          mx[h][3] = fnv(mx[h][3], d[h].w);
+          const uint32_t i = pbase + 8u * h + grp;
+          const uint32_t outw = fnv(fnv(fnv(mx[h][0], mx[h][1]), mx[h][2]), mx[h][3]);
+          if (i < a.n) a.out[8u * i + gl] = outw;
         }
-      }
-#pragma unroll
-      for (uint32_t h = 0; h < kChains; ++h) {
-        const uint32_t i = base + 8u * h + grp;
-        const uint32_t outw = fnv(fnv(fnv(mx[h][0], mx[h][1]), mx[h][2]), mx[h][3]);
-        if (i < a.n) a.out[8u * i + gl] = outw;
       }
     }
   }

@@ -332,7 +332,7 @@ static void alg_work(const hf_task* t, double* bytes, double* ops) {
       break;
     case HF_ETHASH:
       *bytes = (64.0 * 128 + 32) * n;
-      *ops = 64.0 * 40 * n / 8;
+      *ops = (64.0 * 40 / 8 + 80 * 55) * n;  // the walk, then the 80 SHA-512 rounds of the seed
       break;
   }
 }

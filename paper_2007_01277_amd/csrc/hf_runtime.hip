@@ -446,7 +446,7 @@ int64_t useful_wgs(const hf_task* t, const DevTask& d, int waves) {
     case HF_MAXPOOL: units = cdiv(d.pool.row3 ? d.pool.row_units : d.pool.units, waves); break;
     case HF_SHA256D:
     case HF_BLAKE2B: units = cdiv(d.sha.n, 64 * waves); break;
-    case HF_ETHASH: units = cdiv(d.eth.n, EthashLike::kPerWave * waves); break;
+    case HF_ETHASH: units = cdiv(d.eth.n, EthashLike::kPerIter * waves); break;
   }
   return std::max<int64_t>(units, 1);
 }
