@@ -199,10 +199,11 @@ def _eth_table(rows, seed):
     return inputs.eth_table(rows, seed)
 
 
-def hash_case(kind, n, seed=0, nonce0=None, rows=4099, sample=None) -> Case:
+def hash_case(kind, n, seed=0, nonce0=None, rows=4099, sample=None, header=None) -> Case:
     """n instances of a hash kind; the oracle checks every instance, or the first
-    and last 64 plus `sample` drawn ones."""
-    hdr = inputs.header80(seed)
+    and last 64 plus `sample` drawn ones.  `header` (80 bytes) replaces the
+    seeded header."""
+    hdr = inputs.header80(seed) if header is None else np.frombuffer(bytes(header), np.uint8).copy()
     n0 = inputs.nonce0(seed) if nonce0 is None else nonce0 & 0xFFFFFFFF
     hd = dev(hdr.view(np.int32))
     out = torch.full((max(n, 1), 8), 7, dtype=torch.int32, device=DEV)[:n]

@@ -204,6 +204,18 @@ def test_edge_cases_pool_and_hashes():
         G.run_and_check(lambda: H.hf_run_vfused(pr, 512), [c, other])
 
 
+def test_hashes_of_extreme_headers():
+    # all-zero and all-0xFF headers: every 32-bit half of the 64-bit SHA-512 and
+    # BLAKE2b words carries, and the uniform rounds run on extreme values; 96
+    # instances end the Ethash-like walk after its first pass of an iteration,
+    # and a nonce range wraps past 2^32
+    for hdr in (bytes(80), b"\xff" * 80):
+        for k in (H.HF_SHA256D, H.HF_BLAKE2B, H.HF_ETHASH):
+            c = G.hash_case(k, 96, seed=k, nonce0=0xFFFFFFC0, header=hdr)
+            print(c.label, hdr[:1].hex(), flush=True)
+            G.run_and_check(lambda: H.hf_run_solo(c.task, 256), [c])
+
+
 def test_maxpool_ties_nan_and_clamped_windows():
     """Ties keep the first element, NaN propagates, and windows clipped by the
     padding match the oracle's scan -- solo and fused, with and without indices.
