@@ -224,7 +224,7 @@ int hf_run_vfused(const hf_pair* pr, int block, int grid, void* stream, float* m
 /* ---------------------------------------------------------------- resources */
 typedef struct {
   int32_t vgprs;          /* VGPRs per lane of the compiled kernel                   */
-  int32_t sgprs;          /* SGPRs per wave                                          */
+  int32_t sgprs;          /* reserved, 0: the HIP runtime does not report SGPRs      */
   int32_t lds_bytes;      /* static LDS per workgroup                                */
   int32_t spill_bytes;    /* private (scratch) bytes per lane: register spills       */
   int32_t wg_per_cu;      /* resident workgroups per CU at this block size           */
