@@ -5,9 +5,11 @@ Tolerances: the forward pass within 1e-5 of the magnitude of its terms (the
 same network evaluated on |W|, |b| and |x|, which bounds every partial sum);
 gradients within 1e-4 relative to the largest gradient of their layer plus
 1e-4 relative elementwise (fp32 sums over n = 2000 samples); one Adam step
-within 1e-6 absolute on every parameter whose gradient is not tiny.
-Several-step trajectories are not compared: fp32 and fp64 drift apart
-(parity unpinned beyond one step).
+within 1e-6 absolute on every parameter whose gradient is not tiny; five
+steps within 5e-6 (a twentieth of one step's size at lr 1e-3, per step
+1e-6) on the parameters whose gradient stays large at every step.  Where a
+gradient is near zero, Adam's normalised step turns on its fp32 rounding,
+so those parameters are left out of the trajectory check.
 """
 import os
 import tempfile
@@ -85,6 +87,23 @@ def test_adam_step_matches_reference():
     assert np.all(np.abs(p1 - rp)[big] <= 1e-6 + 1e-6 * np.abs(rp[big]))
     # no step is longer than lr, up to the float32 rounding of the update
     assert np.all(np.abs(p1 - p) <= 1e-3 * (1 + 1e-5) + 2.0 ** -22 * np.abs(p))
+
+
+def test_adam_trajectory_follows_reference_for_five_steps():
+    H.hf_mlp_init(D, 11)
+    H.hf_mlp_adam_reset()
+    rp = H.hf_mlp_get_params().astype(np.float64)
+    X, y = _data(500, 12)
+    m, v = np.zeros_like(rp), np.zeros_like(rp)
+    big = np.ones(rp.size, bool)
+    for t in range(1, 6):
+        H.hf_mlp_step(X, y, 1e-3)
+        _, rg = ref.grad(rp, X, y)
+        big &= np.abs(rg) > 1e-3 * np.abs(rg).max()
+        rp, m, v = ref.adam_step(rp, rg, m, v, t, 1e-3)
+    got = H.hf_mlp_get_params().astype(np.float64)
+    assert big.sum() > rp.size // 4
+    assert np.all(np.abs(got - rp)[big] <= 5e-6 + 1e-6 * np.abs(rp[big]))
 
 
 def test_training_fits_a_smooth_target_and_roundtrips_through_a_file():
