@@ -108,7 +108,8 @@ struct EthArgs {  // Ethash-like folds of table rows
   const uint32_t* hdr;  // 20 words: the 80-byte header
   const uint4* table;   // [rows][8] uint4: rows of 128 bytes
   uint32_t* out;        // [n][8] words
-  uint32_t nonce0, n, rows;
+  uint32_t nonce0, n;
+  FastMod rows;         // rows.d: the table's row count
 };
 
 union DevTask {

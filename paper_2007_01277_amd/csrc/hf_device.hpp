@@ -12,6 +12,7 @@
 //                   and lane reads, so the same inputs give the same bits in a
 //                   solo and in a fused kernel, whatever the partition size.
 //  * FastDiv      : division by a run-time constant as multiply-high + shift.
+//  * FastMod      : remainder by a run-time constant for any 32-bit numerator.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -178,6 +179,25 @@ inline FastDiv make_fastdiv(uint32_t d) {
 
 __host__ __device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv& f) {
   return ((uint32_t)(((uint64_t)n * f.m) >> 32) | (n & f.id)) >> f.sh;
+}
+
+// Remainder by a run-time constant d >= 1 for every 32-bit numerator.  With
+// m = floor((2^32 - 1) / d) >= 2^32/d - 1, the estimate q = mulhi(n, m) lies
+// in (n/d - 1 - n/2^32, n/d), so it is floor(n/d) or one less and r = n - q*d
+// lies in [0, 2d); one conditional subtraction finishes it, written as the
+// unsigned minimum of r and r - d (which wraps above r when r < d): five
+// VALU instructions against nine for the compiler's reciprocal sequence.
+struct FastMod {
+  uint32_t d;
+  uint32_t m;
+};
+
+inline FastMod make_fastmod(uint32_t d) { return FastMod{d, d ? 0xFFFFFFFFu / d : 0u}; }
+
+__host__ __device__ __forceinline__ uint32_t fmod32(uint32_t n, const FastMod& f) {
+  const uint32_t r = n - (uint32_t)(((uint64_t)n * f.m) >> 32) * f.d;
+  const uint32_t s = r - f.d;
+  return s < r ? s : r;
 }
 
 }  // namespace hf

@@ -441,7 +441,7 @@ struct EthashLike {
           for (uint32_t h = 0; h < kChains; ++h) {
             const uint32_t comp = cj == 0 ? mx[h][0] : (cj == 1 ? mx[h][1] : (cj == 2 ? mx[h][2] : mx[h][3]));
             const uint32_t mw = (uint32_t)__builtin_amdgcn_ds_bpermute((int)src, (int)comp);
-            const uint32_t row = fnv(j ^ s0[h], mw) % a.rows;
+            const uint32_t row = fmod32(fnv(j ^ s0[h], mw), a.rows);
             d[h] = a.table[(size_t)row * 8u + gl];
           }
 #pragma unroll

@@ -425,7 +425,7 @@ int prepare(const hf_task* t, void* scratch, DevTask* dt) {
       a.out = static_cast<uint32_t*>(t->out0);
       a.nonce0 = (uint32_t)t->p[0];
       a.n = (uint32_t)t->n;
-      a.rows = (uint32_t)t->h;
+      a.rows = make_fastmod((uint32_t)t->h);
       return HF_OK;
     }
   }
